@@ -1,0 +1,267 @@
+"""Benchmark of the iterated stochastic Magnus hot path on one MI355X.
+
+One step = one pass of the whole Magnus path over the batch:
+  iterated integrals of the fine Brownian paths -> Magnus weights
+  -> per-(path, step) logarithm, norm and (m, s) -> Taylor chain over all
+  Magnus steps (register-resident kernel) -> error vs the closed form.
+The Euler-Maruyama baseline is timed the same way at the smallest power-of-two
+step count whose mean error matches the Magnus error (within 2 %), and the
+CPU oracle is timed on a bounded sample of paths on the host cores.
+
+Workload (default): 128x128 grid on [-6,6]^2, constant-coefficient stochastic
+Langevin SPDE (f^x = -v, g^vv = 1, sigma^v = 0.5), Gaussian initial density
+N(0, 0.25 I), T = 1, 1024 paths with 2^14 fine increments, Magnus order 2 with
+16 steps, FP64.  Inputs are synthetic and resident in HBM before timing.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np
+
+FP64_VECTOR_PEAK = 78.6e12           # MI355X FP64 vector, FLOP/s
+HBM_PEAK = 8.0e12                    # MI355X HBM3E, B/s
+# Interior non-zeros per row of the Magnus logarithm of the Langevin operator
+# (f^x = -v, g^vv, sigma^v constant): order 1: B + A -> 5; order 2 adds A^2 and
+# [B,A] -> 11; order 3 adds the double commutators -> 15.  One Taylor term is
+# one product with that matrix plus scaling and accumulation: 2*nnz + 2 flops
+# per grid point.
+NNZ_ROW = {1: 5, 2: 11, 3: 15}
+EULER_FLOPS_PT = 2 * 5 + 1            # u + (dt B + dW A) u: 5 non-zeros per row, + update
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------- CPU oracle
+def _oracle_worker(args):
+    """Runs in a child process: the oracle on a few paths, returns seconds."""
+    name, first, count = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import workloads as wl
+    from oracle import errors, exact, integrals, magnus, operators
+    w = wl.WORKLOADS[name]
+    t0 = time.perf_counter()
+    g = operators.Grid(w.n, w.n, w.lo, w.hi, w.lo, w.hi)
+    B, A = operators.drift_and_noise(g, w.coefficients())
+    basis = operators.magnus_basis(B, A)
+    dW = wl.brownian_increments(w.seed, w.paths, w.Nf, w.T, first=first, count=count)
+    u0 = wl.gaussian_density(w.n, w.n, w.lo, w.hi, w.lo, w.hi, w.s0sq).reshape(-1)
+    coef = integrals.path_coefficients(dW, w.T, w.K, w.order)
+    ps = integrals.path_statistics(dW, w.T)
+    errs = []
+    for p in range(count):
+        uT = magnus.iterated_magnus(basis, coef[p], u0)
+        uex = exact.solution_on_grid(g, w.T, w.a, w.sigma, w.s0sq, ps[p, 0], ps[p, 1])
+        errs.append(errors.relative_error(uex.reshape(w.n, w.n), uT.reshape(w.n, w.n)))
+    return time.perf_counter() - t0, errs
+
+
+def cpu_baseline(name: str):
+    import multiprocessing as mpr
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    per = 2
+    jobs = [(name, i * per, per) for i in range(cores)]
+    ctx = mpr.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    npaths = cores * per
+    return {"value": npaths / wall, "unit": "paths/s", "cores": cores, "kind": "oracle",
+            "sample": f"{npaths} paths of the benchmark workload (paths 0..{npaths - 1}), "
+                      f"{per} per process, integrals + Magnus + error, wall {wall:.1f} s "
+                      f"including operator build",
+            "cpu_seconds": float(sum(r[0] for r in res)),
+            "mean_err": float(np.mean([e for r in res for e in r[1]]))}
+
+
+# ---------------------------------------------------------------- GPU
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="const-128-p1024-m2-k16")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-euler", action="store_true", help="skip the Euler baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: each path is independent "
+                                   "and a multi-GPU run would shard paths (see DESIGN.md); "
+                                   "--gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2207_09776_amd as mg
+    import workloads as wl
+
+    w = wl.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"workload {w.name}: {w.n}^2, P={w.paths}, K={w.K}, order={w.order}, Nf={w.Nf}")
+    N = w.n * w.n
+    coeffs = wl.sample_coefficients(w.coefficients(), w.n, w.n, w.lo, w.hi, w.lo, w.hi)
+    ops = mg.build_operators(w.n, w.n, w.lo, w.hi, w.lo, w.hi, coeffs, w.order)
+    dW = torch.from_numpy(wl.brownian_increments(w.seed, w.paths, w.Nf, w.T)).to(dev)
+    u0 = torch.from_numpy(wl.gaussian_density(w.n, w.n, w.lo, w.hi, w.lo, w.hi, w.s0sq)
+                          .reshape(-1)).to(dev)
+    P, K = w.paths, w.K
+    coef = torch.empty((P, K, 6), dtype=torch.float64, device=dev)
+    ps = torch.empty((P, 2), dtype=torch.float64, device=dev)
+    uT = torch.empty((P, N), dtype=torch.float64, device=dev)
+    err = torch.empty(P, dtype=torch.float64, device=dev)
+    ws = torch.empty(mg.workspace_bytes(ops, P, K), dtype=torch.uint8, device=dev)
+    stats = torch.zeros((P, K, 2), dtype=torch.int32, device=dev)
+
+    def step(with_stats=False):
+        mg.iterated_integrals(dW, w.T, K, w.order, coef=coef, pathstat=ps)
+        _, flags, st = mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws, want_stats=with_stats)
+        mg.error_vs_exact(ops, uT, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T, err=err)
+        return flags, st
+
+    # warm-up (also gives the Taylor statistics and the flags)
+    flags, st = step(with_stats=True)
+    for _ in range(max(0, args.warmup - 1)):
+        step()
+    torch.cuda.synchronize()
+    stats_np = st.cpu().numpy()
+    nflag = int((flags != 0).sum())
+    mean_err = float(err.mean())
+    log(f"warm-up done: mean Err {mean_err:.4e}, flagged paths {nflag}")
+
+    mg.timing_reset()
+    mg.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mg.timing_enable(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    k_ms, k_n = mg.timing_read("expmv")
+    ms_per_step = gpu_ms / args.steps
+    paths_per_s = P / (ms_per_step / 1e3)
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}), "
+        f"Taylor kernel {k_ms / max(k_n, 1):.3f} ms/launch over {k_n} launches")
+
+    # algorithmic work of the dominant kernel (per launch)
+    terms = int(stats_np[..., 0].sum())
+    flops_pt = 2 * NNZ_ROW[w.order] + 2
+    flops = float(terms) * N * flops_pt
+    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    achieved = flops / k_avg_s
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
+                "kernel": "expmv_resident_kernel",
+                "flops_per_point_term": flops_pt, "taylor_terms": terms,
+                "terms_per_path": terms / P, "substeps_per_path": float(stats_np[..., 1].sum()) / P,
+                "launch_ms": k_avg_s * 1e3}
+    # bytes a streaming (HBM-resident) Taylor chain would have to move: read the
+    # term and the partial sum, write both, 8 B each, per point per term
+    streaming_bytes = float(terms) * N * 32
+    extra = {"streaming_equivalent_GBps": streaming_bytes / k_avg_s / 1e9,
+             "hbm_bytes_min_per_launch": float(P * N * 8 + N * 8 + mg.workspace_bytes(ops, P, K))}
+
+    # Euler-Maruyama at matched error
+    euler = None
+    if not args.no_euler:
+        sub = min(64, P)
+        target = 1.02 * float(err[:sub].mean())
+        dWE_full = None
+        chosen = None
+        best = None
+        for q in range(10, int(math.log2(w.Nf)) + 1):
+            NE = 2 ** q
+            dWE = mg.euler_increments(dW[:sub].contiguous(), NE)
+            u = u0.repeat(sub, 1).contiguous()
+            fl = mg.euler_step(ops, u, dWE, w.T / NE)
+            e = mg.error_vs_exact(ops, u, pathstat=ps[:sub].contiguous(), a=w.a, sigma=w.sigma,
+                                  s0sq=w.s0sq, T=w.T)
+            torch.cuda.synchronize()
+            me = float(e.mean()) if int((fl != 0).sum()) == 0 else float("inf")
+            log(f"euler NE=2^{q}: mean Err {me:.4e} (target {target:.4e})")
+            best = (NE, me) if best is None or me < best[1] else best
+            if me <= target:
+                chosen = NE
+                break
+        NE = chosen if chosen is not None else best[0]
+        dWE_full = mg.euler_increments(dW, NE)
+        u = u0.repeat(P, 1).contiguous()
+        mg.euler_step(ops, u, dWE_full, w.T / NE)          # warm-up
+        reps = 2
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            u.copy_(u0.expand(P, N))
+            mg.euler_increments(dW, NE, dWE=dWE_full)
+            mg.euler_step(ops, u, dWE_full, w.T / NE)
+            mg.error_vs_exact(ops, u, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T,
+                              err=err)
+        e1.record()
+        torch.cuda.synchronize()
+        eu_ms = e0.elapsed_time(e1) / reps
+        euler = {"steps": NE, "matched": chosen is not None, "mean_err": float(err.mean()),
+                 "paths_per_s": P / (eu_ms / 1e3), "ms_per_batch": eu_ms,
+                 "magnus_speedup": (P / (ms_per_step / 1e3)) / (P / (eu_ms / 1e3)),
+                 "achieved_TFLOPs": P * NE * N * EULER_FLOPS_PT / (eu_ms / 1e3) / 1e12}
+        log(f"euler at NE={NE}: {euler['paths_per_s']:.1f} paths/s, Err {euler['mean_err']:.4e}")
+
+    cpu = None
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample of paths ...")
+        cpu = cpu_baseline(w.name)
+        log(f"oracle: {cpu['value']:.2f} paths/s on {cpu['cores']} processes")
+
+    out = {
+        "metric": "paths/s at matched L2 error vs exact sol. (Magnus vs Euler, FP32 vs FP64); HBM GB/s",
+        "value": paths_per_s,
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [w.n, w.n], "domain": [w.lo, w.hi],
+                   "paths": P, "magnus_steps": K, "order": w.order, "fine_increments": w.Nf,
+                   "T": w.T, "coefficients": {"fx": "-v", "gvv": w.a, "sv": w.sigma},
+                   "initial": f"N(0,{w.s0sq} I)", "precision": "fp64",
+                   "parallelism": "paths across workgroups, one GPU"},
+        "mean_err_vs_exact": mean_err,
+        "flagged_paths": nflag,
+        "roofline": roofline,
+        "hbm": extra,
+        "euler": euler,
+        "fp32c": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * magnus.h - C ABI of the MI355X (gfx950) iterated stochastic Magnus library.
+ *
+ * Method: Kamm, Pagliarani, Pascucci, "Numerical solution of kinetic SPDEs
+ * via stochastic Magnus expansion" (arXiv 2207.09776).  The library computes,
+ * for many Brownian paths at once, the iterated Magnus scheme of Section 2
+ * ("Iterated Magnus expansion") for the space-discretised SPDE
+ * eq. (generalSPDE) -> eq. (SPDEvec):
+ *
+ *     u_{k+1} = exp(Y_{p,k}) u_k,   Y_{p,k} = sum_l c_{p,k,l} M_l,
+ *     M = (B, A, A^2, [B,A], [[B,A],A], [[B,A],B])      (eq. (MagnusFormulas))
+ *
+ * plus the Euler-Maruyama baseline (eq. (EulerMaruyama)) and the error norm
+ * of eq. (meanErr) against the closed-form Langevin solution (Section 3.1).
+ *
+ * Conventions shared by every entry point
+ *   - A grid function has N = nx*nv entries stored [nv][nx], x fastest: the
+ *     column stacking vec of Section 2.  Batches are [P][nv][nx].
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are ordinary host memory owned by the caller.  The library
+ *     never frees or keeps caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Compute calls are asynchronous on that stream: they enqueue kernels and
+ *     return; results (including per-path flags) are valid after the stream
+ *     is synchronised.  They do not allocate device memory or synchronise.
+ *   - Return value: MG_OK or a negative mg_status for argument, shape, support
+ *     or launch errors, detected on the host before anything is enqueued (a
+ *     launch error after enqueueing returns MG_EHIP).  mg_last_error() gives a
+ *     message for the calling thread.  Numerical trouble inside a path (a
+ *     non-finite value, or a step beyond the convergence radius of the Magnus
+ *     expansion, Theorem 'convergence') does not abort the batch: it is
+ *     reported per path in the `flags` array.
+ */
+#ifndef MAGNUS_H
+#define MAGNUS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mg_status;
+#define MG_OK            0
+#define MG_EINVAL       (-1)   /* bad argument value or NULL pointer         */
+#define MG_ESHAPE       (-2)   /* inconsistent sizes                         */
+#define MG_EUNSUPPORTED (-3)   /* valid input this build does not implement  */
+#define MG_EHIP         (-4)   /* HIP runtime error                          */
+#define MG_ENOMEM       (-5)   /* host allocation failed / workspace too small */
+
+/* Per-path flag bits written to `flags[p]` (0 = path finished normally). */
+#define MG_FLAG_NONFINITE 1    /* a NaN or Inf appeared in the path's state   */
+#define MG_FLAG_NORM      2    /* ||Y_{p,k} - mu I||_1 exceeded the supported range */
+
+/* Precision forms of the Taylor chain (the state u is FP64 in both). */
+#define MG_FP64  0             /* every operation in FP64                     */
+#define MG_FP32C 1             /* FP32 stencil products with a compensated FP32
+                                  Taylor sum; FP64 norm, (m,s) choice, e^{mu/s}
+                                  scaling and state between Magnus steps       */
+
+/* Homogeneous grids of eq. (xGrid)/(vGrid): interior nodes
+ * x_i = ax + i*(bx-ax)/(nx+1), i = 1..nx (same for v); u = 0 on the boundary. */
+typedef struct {
+    int32_t nx, nv;
+    double ax, bx, av, bv;
+} mg_grid;
+
+/* Coefficient grids of eq. (generalSPDE), host arrays of nx*nv doubles in
+ * [nv][nx] order; NULL means identically zero.  This build supports
+ * coefficients that depend on v only (constant along x) for h, fx, fv, gxv,
+ * gvv, sig, sv, with gxx = sx = 0: the constant- and v-dependent stochastic
+ * Langevin SPDE (eq. (coeffsLangevinConst)).  Anything else returns
+ * MG_EUNSUPPORTED. */
+typedef struct {
+    const double *h, *fx, *fv, *gxx, *gxv, *gvv, *sig, *sx, *sv;
+} mg_coeffs;
+
+/* Parameters of the closed-form constant-coefficient solution (Section 3.1):
+ * g^vv = a, sigma^v = sigma (0 < sigma^2 < a), Gaussian initial density
+ * N(0, s0sq I), time T. */
+typedef struct {
+    double a, sigma, s0sq, T;
+} mg_exact;
+
+/* Opaque operator set built once per (grid, coefficients, order). */
+typedef struct mg_ops mg_ops;
+
+/* --------------------------------------------------------------------------
+ * mg_build_operators  (Section 2, "Computation of A and B"; eq. (MagnusFormulas))
+ *
+ * Builds on the host, in FP64, the drift B and noise A of eq. (SPDEvec) and
+ * the commutators needed by Magnus order `order` (1..3) as exact products of
+ * the truncated matrices, in the factored form
+ *     M_l = sum_{q=0..2} V_{l,q} (x) (D^x)^q,  V_{l,q} banded nv x nv,
+ * and uploads the tables to the current HIP device.
+ *   grid, coeffs : host, read during the call only.
+ *   out          : receives a library-owned handle; free with
+ *                  mg_free_operators.  The handle is immutable after build and
+ *                  may be used from several streams at once.
+ * Errors: MG_EINVAL (NULL, order outside 1..3, nx or nv < 1, empty domain),
+ *         MG_EUNSUPPORTED (coefficients outside the supported set, nx > 128
+ *         and nv > 1024 combinations this build has no kernel for),
+ *         MG_EHIP, MG_ENOMEM.
+ * ------------------------------------------------------------------------ */
+mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32_t order,
+                             mg_ops** out);
+
+/* Frees a handle from mg_build_operators (NULL is accepted).  The caller must
+ * make sure no enqueued work still uses it. */
+mg_status mg_free_operators(mg_ops* ops);
+
+/* --------------------------------------------------------------------------
+ * mg_iterated_integrals  (eq. (MagnusFormulas); Section 3 "Implementation")
+ *
+ * For each path p and Magnus step k (sub-interval of length h = T/K, path
+ * restarted at its left end) computes from the fine increments the weights
+ *   c0 = h, c1 = dW, c2 = -h/2, c3 = I1 - h dW/2,
+ *   c4 = I2/2 - dW I1/2 + h dW^2/12, c5 = J - h I1/2 - h^2 dW/12
+ * with I1 = int W, I2 = int W^2, J = int r W dr over the sub-interval, taken
+ * exactly for the piecewise-linear path through the fine nodes.  Weights
+ * beyond `order` are written as 0.  Also writes per path (W_T, int_0^T W).
+ *   dW       : device, [P][Nf] fine increments (delta = T/Nf).
+ *   coef     : device, [P][K][6] output.
+ *   pathstat : device, [P][2] output (may be NULL).
+ * Errors: MG_EINVAL (NULL, T <= 0, order outside 1..3), MG_ESHAPE (P < 0,
+ *         K < 1, Nf < 1, Nf % K != 0).  P = 0 is a no-op.
+ * ------------------------------------------------------------------------ */
+mg_status mg_iterated_integrals(const double* dW, int64_t P, int64_t Nf, double T, int32_t K,
+                                int32_t order, double* coef, double* pathstat, void* stream);
+
+/* Bytes of device workspace mg_magnus_expmv needs for P paths and K steps. */
+size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t precision);
+
+/* --------------------------------------------------------------------------
+ * mg_magnus_expmv  (Section 2, "Iterated Magnus expansion"; the action of the
+ *                   matrix exponential, Section 3 "Implementation")
+ *
+ * uT[p] = exp(Y_{p,K-1}) ... exp(Y_{p,0}) u0[p], Y_{p,k} = sum_l coef[p][k][l] M_l.
+ * Each factor is applied matrix-free by the truncated Taylor series with
+ * trace shift mu = tr(Y)/N and s scaling steps chosen from ||Y - mu I||_1
+ * (Al-Mohy-Higham thresholds for `tol`), stopping a Taylor sum early once two
+ * consecutive terms are below tol * ||partial sum||_inf.
+ *   coef      : device, [P][K][6] weights (mg_iterated_integrals layout).
+ *   u0        : device FP64, [N] if u0_broadcast != 0 else [P][N].
+ *   uT        : device FP64, [P][N] output (may not alias coef or ws).
+ *   precision : MG_FP64 or MG_FP32C.
+ *   tol       : Taylor tolerance; <= 0 selects 2^-53 (FP64) / 2^-24 (FP32C).
+ *   ws        : device workspace of ws_bytes >= mg_workspace_bytes(...).
+ *   stats     : device int32 [P][K][2] = (Taylor terms applied, s), or NULL.
+ *   flags     : device int32 [P] (MG_FLAG_* bits), or NULL.
+ * Errors: MG_EINVAL, MG_ESHAPE (P < 0, K < 1), MG_EUNSUPPORTED (precision or
+ *         size without a kernel), MG_ENOMEM (ws too small), MG_EHIP.
+ * P = 0 is a no-op.
+ * ------------------------------------------------------------------------ */
+mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
+                          const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
+                          double tol, void* ws, size_t ws_bytes, int32_t* stats, int32_t* flags,
+                          void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_euler_increments  (eq. (EulerMaruyama): Delta W_{t_k} = W_{t_{k+1}} - W_{t_k})
+ *
+ * dWE[p][n] = sum of the Nf/NE fine increments dW[p][n*Nf/NE .. (n+1)*Nf/NE - 1],
+ * the Brownian increment of Euler step n on the same path.
+ *   dW  : device FP64 [P][Nf];  dWE : device FP64 [P][NE] output.
+ * Errors: MG_EINVAL (NULL), MG_ESHAPE (P < 0, NE < 1, Nf % NE != 0).
+ * ------------------------------------------------------------------------ */
+mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t NE, double* dWE,
+                              void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_euler_step  (eq. (EulerMaruyama))
+ *
+ * Runs NE Euler-Maruyama steps in place on every path:
+ *     u <- u + dt * B u + dWE[p][n] * A u,   n = 0..NE-1,
+ * with the B and A of `ops` (built at any order).
+ *   u     : device FP64 [P][N], updated in place.
+ *   dWE   : device FP64 [P][NE], the Brownian increment of each Euler step.
+ *   flags : device int32 [P] or NULL (MG_FLAG_NONFINITE).
+ *   precision must be MG_FP64.  ws/ws_bytes are reserved (pass NULL, 0).
+ * Errors: MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP.  P = 0 or NE = 0
+ * is a no-op.
+ * ------------------------------------------------------------------------ */
+mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* dWE, int32_t NE,
+                        double dt, int32_t precision, void* ws, size_t ws_bytes, int32_t* flags,
+                        void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_error_vs_exact  (eq. (meanErr); closed form of Section 3.1)
+ *
+ * err[p] = ||U_ref - U_p||_F / ||U_ref||_F over the central window I^kappa x
+ * I^kappa (0-based indices i0 .. i0 + floor(n/2^kappa) - 1 with
+ * i0 = floor(n/2 - n/2^(kappa+1)), per axis).  U_ref is uref[p] when uref is
+ * not NULL, else the closed-form solution at time ex->T of the SPDE with
+ * f^x = -v, g^vv = a, sigma^v = sigma and initial density N(0, s0sq I),
+ * evaluated from pathstat[p] = (W_T, int_0^T W).
+ *   grid     : host.  ex : host (unused when uref != NULL).
+ *   pathstat : device [P][2] (unused when uref != NULL).
+ *   u, uref  : device FP64 [P][N].   err : device FP64 [P] output.
+ * Errors: MG_EINVAL (NULL, kappa < 0, window empty, sigma^2 >= a),
+ *         MG_ESHAPE, MG_EHIP.  The mean over paths (Err) is left to the caller.
+ * ------------------------------------------------------------------------ */
+mg_status mg_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const double* pathstat,
+                            const double* u, const double* uref, int64_t P, int32_t kappa,
+                            double* err, void* stream);
+
+/* Message describing the last failing call on this thread ("" if none). */
+const char* mg_last_error(void);
+
+/* --------------------------------------------------------------------------
+ * Kernel timing (instrumentation, not part of the method).  While enabled,
+ * every launch of the Taylor-chain kernel inside mg_magnus_expmv and of the
+ * Euler kernel is bracketed by HIP events recorded on the caller's stream.
+ * mg_timing_read synchronises those events and returns the summed kernel
+ * time in milliseconds and the number of launches for "expmv" or "euler".
+ * Enabling allocates host-side event objects; do not enable under graph
+ * capture.
+ * ------------------------------------------------------------------------ */
+mg_status mg_timing_enable(int32_t on);
+mg_status mg_timing_read(const char* kernel, double* total_ms, int64_t* launches);
+mg_status mg_timing_reset(void);
+
+/* Library version string. */
+const char* mg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MAGNUS_H */

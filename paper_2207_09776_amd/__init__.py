@@ -1,0 +1,257 @@
+"""Python binding of libmagnus (include/magnus.h): the iterated stochastic
+Magnus scheme of arXiv 2207.09776 on MI355X (gfx950).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+PyTorch provides device memory and the current HIP stream.  Importing works
+without a GPU; calling a compute function needs the built library
+(``python -m paper_2207_09776_amd.build``) and a GPU, and raises otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmagnus.so")
+
+MG_OK, MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP, MG_ENOMEM = 0, -1, -2, -3, -4, -5
+MG_FLAG_NONFINITE, MG_FLAG_NORM = 1, 2
+MG_FP64, MG_FP32C = 0, 1
+PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
+
+EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
+           "mg_workspace_bytes", "mg_magnus_expmv", "mg_euler_increments", "mg_euler_step",
+           "mg_error_vs_exact",
+           "mg_last_error", "mg_timing_enable", "mg_timing_read", "mg_timing_reset", "mg_version")
+
+
+class MagnusError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class mg_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nv", ctypes.c_int32), ("ax", ctypes.c_double),
+                ("bx", ctypes.c_double), ("av", ctypes.c_double), ("bv", ctypes.c_double)]
+
+
+class mg_coeffs(ctypes.Structure):
+    _fields_ = [(n, ctypes.POINTER(ctypes.c_double))
+                for n in ("h", "fx", "fv", "gxx", "gxv", "gvv", "sig", "sx", "sv")]
+
+
+class mg_exact(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("sigma", ctypes.c_double), ("s0sq", ctypes.c_double),
+                ("T", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmagnus.so once; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with python -m paper_2207_09776_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.mg_build_operators.argtypes = [ctypes.POINTER(mg_grid), ctypes.POINTER(mg_coeffs), i32,
+                                       ctypes.POINTER(vp)]
+    lib.mg_free_operators.argtypes = [vp]
+    lib.mg_iterated_integrals.argtypes = [vp, i64, i64, dbl, i32, i32, vp, vp, vp]
+    lib.mg_workspace_bytes.argtypes = [vp, i64, i32, i32]
+    lib.mg_workspace_bytes.restype = sz
+    lib.mg_magnus_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, vp, vp, vp]
+    lib.mg_euler_step.argtypes = [vp, vp, i64, vp, i32, dbl, i32, vp, sz, vp, vp]
+    lib.mg_euler_increments.argtypes = [vp, i64, i64, i32, vp, vp]
+    lib.mg_error_vs_exact.argtypes = [ctypes.POINTER(mg_grid), ctypes.POINTER(mg_exact), vp, vp,
+                                      vp, i64, i32, vp, vp]
+    lib.mg_last_error.restype = ctypes.c_char_p
+    lib.mg_version.restype = ctypes.c_char_p
+    lib.mg_timing_enable.argtypes = [i32]
+    lib.mg_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    for name in ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
+                 "mg_magnus_expmv", "mg_euler_increments", "mg_euler_step", "mg_error_vs_exact", "mg_timing_enable",
+                 "mg_timing_read", "mg_timing_reset"):
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != MG_OK:
+        msg = load_library().mg_last_error().decode()
+        raise MagnusError(code, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+
+
+class Operators:
+    """mg_build_operators handle (library-owned tables on the current device)."""
+
+    def __init__(self, nx: int, nv: int, ax: float, bx: float, av: float, bv: float,
+                 coeffs: Dict[str, Optional[np.ndarray]], order: int):
+        lib = load_library()
+        self.grid = mg_grid(nx, nv, ax, bx, av, bv)
+        self.order = order
+        keep = {}
+        c = mg_coeffs()
+        for name, _ in mg_coeffs._fields_:
+            arr = coeffs.get(name)
+            if arr is None:
+                setattr(c, name, None)
+                continue
+            a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
+            if a.size != nx * nv:
+                raise ValueError(f"coefficient {name} must have nx*nv entries")
+            keep[name] = a
+            setattr(c, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        h = ctypes.c_void_p()
+        _check(lib.mg_build_operators(ctypes.byref(self.grid), ctypes.byref(c), order,
+                                      ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().mg_free_operators(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_operators(nx, nv, ax, bx, av, bv, coeffs, order) -> Operators:
+    return Operators(nx, nv, ax, bx, av, bv, coeffs, order)
+
+
+def iterated_integrals(dW, T: float, K: int, order: int, coef=None, pathstat=None, stream=None):
+    """mg_iterated_integrals: dW [P][Nf] float64 CUDA -> (coef [P][K][6], pathstat [P][2])."""
+    import torch
+    _dev_f64(dW, "dW")
+    P, Nf = dW.shape
+    if coef is None:
+        coef = torch.empty((P, K, 6), dtype=torch.float64, device=dW.device)
+    if pathstat is None:
+        pathstat = torch.empty((P, 2), dtype=torch.float64, device=dW.device)
+    _check(load_library().mg_iterated_integrals(_ptr(dW), P, Nf, float(T), K, order, _ptr(coef),
+                                                _ptr(pathstat), _stream(stream)))
+    return coef, pathstat
+
+
+def workspace_bytes(ops: Operators, P: int, K: int, precision: str = "fp64") -> int:
+    return int(load_library().mg_workspace_bytes(ops.handle, P, K, PRECISIONS[precision]))
+
+
+def magnus_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float = 0.0,
+                 uT=None, ws=None, want_stats: bool = False, stream=None):
+    """mg_magnus_expmv.  u0: [N] (shared) or [P][N].  Returns (uT, flags, stats)."""
+    import torch
+    _dev_f64(coef, "coef")
+    _dev_f64(u0, "u0")
+    P, K, six = coef.shape
+    N = ops.grid.nx * ops.grid.nv
+    bcast = 1 if u0.dim() == 1 else 0
+    if u0.numel() != (N if bcast else P * N):
+        raise ValueError("u0 has the wrong size")
+    dev = coef.device
+    if uT is None:
+        uT = torch.empty((P, N), dtype=torch.float64, device=dev)
+    need = workspace_bytes(ops, P, K, precision)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    flags = torch.zeros(P, dtype=torch.int32, device=dev)
+    stats = torch.zeros((P, K, 2), dtype=torch.int32, device=dev) if want_stats else None
+    _check(load_library().mg_magnus_expmv(
+        ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
+        float(tol), _ptr(ws), ws.numel(), _ptr(stats), _ptr(flags), _stream(stream)))
+    return uT, flags, stats
+
+
+def euler_increments(dW, NE: int, dWE=None, stream=None):
+    """mg_euler_increments: [P][Nf] fine increments -> [P][NE] Euler increments."""
+    import torch
+    _dev_f64(dW, "dW")
+    P, Nf = dW.shape
+    if dWE is None:
+        dWE = torch.empty((P, NE), dtype=torch.float64, device=dW.device)
+    _check(load_library().mg_euler_increments(_ptr(dW), P, Nf, NE, _ptr(dWE), _stream(stream)))
+    return dWE
+
+
+def euler_step(ops: Operators, u, dWE, dt: float, stream=None):
+    """mg_euler_step: NE Euler-Maruyama steps in place on u [P][N]; returns flags."""
+    import torch
+    _dev_f64(u, "u")
+    _dev_f64(dWE, "dWE")
+    P, NE = dWE.shape
+    flags = torch.zeros(P, dtype=torch.int32, device=u.device)
+    _check(load_library().mg_euler_step(ops.handle, _ptr(u), P, _ptr(dWE), NE, float(dt), MG_FP64,
+                                        None, 0, _ptr(flags), _stream(stream)))
+    return flags
+
+
+def error_vs_exact(ops_or_grid, u, pathstat=None, a=None, sigma=None, s0sq=None, T=None,
+                   uref=None, kappa: int = 0, err=None, stream=None):
+    """mg_error_vs_exact: per-path relative Frobenius error on the kappa window."""
+    import torch
+    grid = ops_or_grid.grid if isinstance(ops_or_grid, Operators) else ops_or_grid
+    _dev_f64(u, "u")
+    P = u.shape[0]
+    if err is None:
+        err = torch.empty(P, dtype=torch.float64, device=u.device)
+    ex = None
+    if uref is None:
+        _dev_f64(pathstat, "pathstat")
+        ex = mg_exact(a, sigma, s0sq, T)
+    else:
+        _dev_f64(uref, "uref")
+    _check(load_library().mg_error_vs_exact(
+        ctypes.byref(grid), ctypes.byref(ex) if ex is not None else None, _ptr(pathstat), _ptr(u),
+        _ptr(uref), P, kappa, _ptr(err), _stream(stream)))
+    return err
+
+
+def timing_enable(on: bool = True):
+    _check(load_library().mg_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load_library().mg_timing_reset())
+
+
+def timing_read(kernel: str):
+    """(total milliseconds, launches) of the named kernel since the last reset."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load_library().mg_timing_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

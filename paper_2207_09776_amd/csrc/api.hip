@@ -1,0 +1,260 @@
+// C ABI of the library: argument checking, workspace layout, kernel launches.
+// Every check happens on the host before anything is enqueued.
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "mg_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+// ---- kernel timing (instrumentation) ---------------------------------------
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t start, stop;
+};
+std::mutex g_timing_mu;
+bool g_timing_on = false;
+std::vector<TimedLaunch> g_timed;
+
+struct TimingScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    const char* name;
+    bool on;
+    TimingScope(const char* n, hipStream_t st) : s(st), name(n) {
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        on = g_timing_on;
+        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, s);
+        else
+            on = false;
+    }
+    void done() {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_timing_mu);
+        g_timed.push_back({name, a, b});
+        on = false;
+    }
+};
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+mg_status hip_fail(hipError_t e, const char* where) {
+    return mg_fail(MG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+mg_status mg_fail(mg_status code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_last_error.c_str(); }
+
+const char* mg_version(void) { return "magnus-mi355x 0.1 (gfx950)"; }
+
+mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32_t order,
+                             mg_ops** out) {
+    g_last_error.clear();
+    if (!grid || !coeffs || !out) return mg_fail(MG_EINVAL, "mg_build_operators: NULL argument");
+    *out = nullptr;
+    if (order < 1 || order > 3) return mg_fail(MG_EINVAL, "mg_build_operators: order must be 1..3");
+    if (grid->nx < 1 || grid->nv < 1 || grid->nx > 8192 || grid->nv > 8192)
+        return mg_fail(MG_EINVAL, "mg_build_operators: nx and nv must be in 1..8192");
+    if (!is_finite(grid->ax) || !is_finite(grid->bx) || !is_finite(grid->av) || !is_finite(grid->bv) ||
+        !(grid->bx > grid->ax) || !(grid->bv > grid->av))
+        return mg_fail(MG_EINVAL, "mg_build_operators: empty or non-finite domain");
+    mg_ops* ops = new (std::nothrow) mg_ops();
+    if (!ops) return mg_fail(MG_ENOMEM, "mg_build_operators: out of host memory");
+    mg_status st;
+    try {
+        st = mg_build_host(grid, coeffs, order, ops);
+    } catch (const std::bad_alloc&) {
+        st = mg_fail(MG_ENOMEM, "mg_build_operators: out of host memory");
+    }
+    if (st != MG_OK) {
+        delete ops;
+        return st;
+    }
+    hipError_t e = hipGetDevice(&ops->device);
+    const size_t bytes = ops->basis_host.size() * sizeof(double);
+    if (e == hipSuccess) e = hipMalloc((void**)&ops->basis_dev, bytes);
+    if (e == hipSuccess)
+        e = hipMemcpy(ops->basis_dev, ops->basis_host.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (ops->basis_dev) (void)hipFree(ops->basis_dev);
+        delete ops;
+        return hip_fail(e, "mg_build_operators");
+    }
+    *out = ops;
+    return MG_OK;
+}
+
+mg_status mg_free_operators(mg_ops* ops) {
+    if (!ops) return MG_OK;
+    hipError_t e = hipSuccess;
+    if (ops->basis_dev) e = hipFree(ops->basis_dev);
+    delete ops;
+    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_free_operators");
+}
+
+mg_status mg_iterated_integrals(const double* dW, int64_t P, int64_t Nf, double T, int32_t K,
+                                int32_t order, double* coef, double* pathstat, void* stream) {
+    g_last_error.clear();
+    if (P < 0 || K < 1 || Nf < 1) return mg_fail(MG_ESHAPE, "mg_iterated_integrals: need P >= 0, K >= 1, Nf >= 1");
+    if (Nf % K != 0) return mg_fail(MG_ESHAPE, "mg_iterated_integrals: Nf must be a multiple of K");
+    if (P > 0x7fffffff) return mg_fail(MG_ESHAPE, "mg_iterated_integrals: P too large");
+    if (!(T > 0.0) || !is_finite(T)) return mg_fail(MG_EINVAL, "mg_iterated_integrals: T must be positive");
+    if (order < 1 || order > 3) return mg_fail(MG_EINVAL, "mg_iterated_integrals: order must be 1..3");
+    if (P == 0) return MG_OK;
+    if (!dW || !coef) return mg_fail(MG_EINVAL, "mg_iterated_integrals: NULL pointer");
+    hipError_t e = launch_iterated_integrals(dW, P, Nf, T, K, order, coef, pathstat,
+                                             (hipStream_t)stream);
+    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_iterated_integrals");
+}
+
+mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t NE, double* dWE,
+                              void* stream) {
+    g_last_error.clear();
+    if (P < 0 || NE < 1 || Nf < 1) return mg_fail(MG_ESHAPE, "mg_euler_increments: need P >= 0, NE >= 1, Nf >= 1");
+    if (Nf % NE != 0) return mg_fail(MG_ESHAPE, "mg_euler_increments: Nf must be a multiple of NE");
+    if (P > ((int64_t)1 << 40) / NE) return mg_fail(MG_ESHAPE, "mg_euler_increments: P*NE too large");
+    if (P == 0) return MG_OK;
+    if (!dW || !dWE) return mg_fail(MG_EINVAL, "mg_euler_increments: NULL pointer");
+    hipError_t e = launch_euler_increments(dW, P, Nf, NE, dWE, (hipStream_t)stream);
+    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_euler_increments");
+}
+
+size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t precision) {
+    (void)precision;
+    if (!ops || P <= 0 || K <= 0) return 0;
+    return (size_t)P * (size_t)K * mg_table_stride(ops) * sizeof(double);
+}
+
+mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
+                          const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
+                          double tol, void* ws, size_t ws_bytes, int32_t* stats, int32_t* flags,
+                          void* stream) {
+    g_last_error.clear();
+    if (!ops) return mg_fail(MG_EINVAL, "mg_magnus_expmv: NULL ops");
+    if (P < 0 || K < 1) return mg_fail(MG_ESHAPE, "mg_magnus_expmv: need P >= 0 and K >= 1");
+    if (P > 0x7fffffff / (int64_t)K) return mg_fail(MG_ESHAPE, "mg_magnus_expmv: P*K too large");
+    if (precision != MG_FP64 && precision != MG_FP32C)
+        return mg_fail(MG_EINVAL, "mg_magnus_expmv: unknown precision");
+    if (precision == MG_FP32C)
+        return mg_fail(MG_EUNSUPPORTED, "mg_magnus_expmv: MG_FP32C is not built yet");
+    if (!(tol == tol) || tol >= 1.0) return mg_fail(MG_EINVAL, "mg_magnus_expmv: tol must be < 1");
+    if (tol <= 0.0) tol = precision == MG_FP64 ? 0x1p-53 : 0x1p-24;
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_expmv_resident(ops, nullptr, P, K, nullptr, 0, nullptr, tol, nullptr, nullptr, s,
+                              true) != hipSuccess)
+        return mg_fail(MG_EUNSUPPORTED, "mg_magnus_expmv: no kernel for this grid size");
+    if (P == 0) return MG_OK;
+    if (!coef || !u0 || !uT || !ws) return mg_fail(MG_EINVAL, "mg_magnus_expmv: NULL pointer");
+    const size_t need = mg_workspace_bytes(ops, P, K, precision);
+    if (ws_bytes < need)
+        return mg_fail(MG_ENOMEM, "mg_magnus_expmv: workspace smaller than mg_workspace_bytes()");
+    double* tables = (double*)ws;
+    hipError_t e = launch_assemble(ops, coef, P, K, tol, precision, tables, s);
+    if (e != hipSuccess) return hip_fail(e, "mg_magnus_expmv (assemble)");
+    TimingScope ts("expmv", s);
+    e = launch_expmv_resident(ops, tables, P, K, u0, u0_broadcast, uT, tol, stats, flags, s,
+                              false);
+    ts.done();
+    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_magnus_expmv");
+}
+
+mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* dWE, int32_t NE,
+                        double dt, int32_t precision, void* ws, size_t ws_bytes, int32_t* flags,
+                        void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    g_last_error.clear();
+    if (!ops) return mg_fail(MG_EINVAL, "mg_euler_step: NULL ops");
+    if (P < 0 || NE < 0) return mg_fail(MG_ESHAPE, "mg_euler_step: need P >= 0 and NE >= 0");
+    if (P > 0x7fffffff) return mg_fail(MG_ESHAPE, "mg_euler_step: P too large");
+    if (precision != MG_FP64) return mg_fail(MG_EUNSUPPORTED, "mg_euler_step: only MG_FP64");
+    if (!is_finite(dt)) return mg_fail(MG_EINVAL, "mg_euler_step: dt must be finite");
+    hipStream_t s = (hipStream_t)stream;
+    if (launch_euler_resident(ops, nullptr, P, nullptr, NE, dt, nullptr, s, true) != hipSuccess)
+        return mg_fail(MG_EUNSUPPORTED, "mg_euler_step: no kernel for this grid size");
+    if (P == 0 || NE == 0) return MG_OK;
+    if (!u || !dWE) return mg_fail(MG_EINVAL, "mg_euler_step: NULL pointer");
+    TimingScope ts("euler", s);
+    hipError_t e = launch_euler_resident(ops, u, P, dWE, NE, dt, flags, s, false);
+    ts.done();
+    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_euler_step");
+}
+
+mg_status mg_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const double* pathstat,
+                            const double* u, const double* uref, int64_t P, int32_t kappa,
+                            double* err, void* stream) {
+    g_last_error.clear();
+    if (!grid) return mg_fail(MG_EINVAL, "mg_error_vs_exact: NULL grid");
+    if (P < 0 || P > 0x7fffffff) return mg_fail(MG_ESHAPE, "mg_error_vs_exact: bad P");
+    if (grid->nx < 1 || grid->nv < 1 || !(grid->bx > grid->ax) || !(grid->bv > grid->av))
+        return mg_fail(MG_EINVAL, "mg_error_vs_exact: bad grid");
+    if (kappa < 0 || kappa > 30 || (grid->nx >> kappa) < 1 || (grid->nv >> kappa) < 1)
+        return mg_fail(MG_EINVAL, "mg_error_vs_exact: kappa window is empty");
+    if (!uref) {
+        if (!ex) return mg_fail(MG_EINVAL, "mg_error_vs_exact: NULL exact parameters");
+        if (!(ex->sigma * ex->sigma < ex->a) || !(ex->s0sq > 0.0) || !(ex->T > 0.0))
+            return mg_fail(MG_EINVAL, "mg_error_vs_exact: need sigma^2 < a, s0sq > 0, T > 0");
+    }
+    if (P == 0) return MG_OK;
+    if (!u || !err || (!uref && !pathstat))
+        return mg_fail(MG_EINVAL, "mg_error_vs_exact: NULL pointer");
+    hipError_t e = launch_error_vs_exact(grid, ex, pathstat, u, uref, P, kappa, err,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_error_vs_exact");
+}
+
+mg_status mg_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    g_timing_on = on != 0;
+    return MG_OK;
+}
+
+mg_status mg_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    for (auto& t : g_timed) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    g_timed.clear();
+    return MG_OK;
+}
+
+mg_status mg_timing_read(const char* kernel, double* total_ms, int64_t* launches) {
+    g_last_error.clear();
+    if (!kernel || !total_ms || !launches) return mg_fail(MG_EINVAL, "mg_timing_read: NULL");
+    std::lock_guard<std::mutex> lk(g_timing_mu);
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto& t : g_timed) {
+        if (t.name != kernel) continue;
+        hipError_t e = hipEventSynchronize(t.stop);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.start, t.stop);
+        if (e != hipSuccess) return hip_fail(e, "mg_timing_read");
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return MG_OK;
+}
+
+}  // extern "C"

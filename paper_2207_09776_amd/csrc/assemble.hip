@@ -1,0 +1,178 @@
+// Per-(path, step) assembly of the Magnus logarithm, its 1-norm and the
+// Taylor parameters (m, s).
+//
+// Y_{p,k} = sum_l coef[p][k][l] M_l (eq. (MagnusFormulas)) is formed row by
+// row from the factored basis tables.  mu = tr(Y)/N is removed from the
+// diagonal, ||Y - mu I||_1 (maximum absolute column sum) is computed exactly
+// from the factored form, and (m, s) minimise m * s subject to
+// ||Y - mu I||_1 / s <= theta_m (truncated-Taylor thresholds of Al-Mohy and
+// Higham for the requested tolerance).  The table written for (p, k) holds the
+// header (s, m, exp(mu/s), mu, norm, flag) and the rows of (Y - mu I)/s.
+//
+// Column sums.  With M = sum_q V_q (x) Dt^q (Dt = tridiag(-1,0,1)), column
+// (i', j') of Y - mu I has entries in rows (i, j), |j - j'| <= R, i - i' in
+// {-2..2}:   i'-2: a2,  i'-1: a1,  i': a0 + a2 * diag(Dt^2)_{i'},  i'+1: -a1,
+// i'+2: a2, with a_q = V_q[j][j' - j] (entries outside the grid are absent).
+// Columns i' = 2 .. nx-3 share one pattern, so the classes
+// i' in {0, 1, 2, nx-3, nx-2, nx-1} cover all columns.
+
+#include <cmath>
+
+#include "mg_internal.h"
+#include "theta_table.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxS = 1 << 14;   // beyond this the path is flagged (MG_FLAG_NORM)
+
+struct AsmArgs {
+    const double* basis;       // [6][nv][NBP]
+    const double* coef;        // [P][K][6]
+    double* tables;            // [P][K][tstride]
+    size_t tstride;
+    int nx, nv, nv_pad, K, NBP, nact;
+    int R0, R1, R2;
+    int use24;                 // theta table for 2^-24 instead of 2^-53
+};
+
+__device__ inline double coeff(const AsmArgs& a, const double* c, int j, int idx) {
+    double v = 0.0;
+    for (int l = 0; l < a.nact; ++l) v += c[l] * a.basis[((size_t)l * a.nv_pad + j) * a.NBP + idx];
+    return v;
+}
+
+__device__ inline double block_reduce(double v, double* red, bool is_max) {
+    for (int o = 32; o > 0; o >>= 1) {
+        double u = __shfl_xor(v, o, 64);
+        v = is_max ? fmax(v, u) : v + u;
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < kThreads / 64; ++i) s = is_max ? fmax(s, red[i]) : s + red[i];
+    return s;
+}
+
+// diagonal of Dt^2 at column/row i (Dt = tridiag(-1,0,1) with zero boundary)
+__device__ inline double dt2_diag(int i, int nx) {
+    int cnt = (i + 1 < nx ? 1 : 0) + (i > 0 ? 1 : 0);
+    return -(double)cnt;
+}
+
+__global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
+    __shared__ double red[kThreads / 64];
+    __shared__ double hdr[4];
+    const int64_t pk = blockIdx.x;
+    const double* c = a.coef + pk * 6;
+    const int t = threadIdx.x;
+    const int o0 = 0, o1 = 2 * a.R0 + 1, o2 = o1 + 2 * a.R1 + 1;
+    const int nx = a.nx, nv = a.nv;
+
+    // trace: sum_j (nx * V0[j][0] + tr(Dt^2) * V2[j][0])
+    const double trDt2 = nx >= 2 ? -(2.0 * nx - 2.0) : 0.0;
+    double tr = 0.0;
+    for (int j = t; j < nv; j += kThreads)
+        tr += nx * coeff(a, c, j, o0 + a.R0) + trDt2 * coeff(a, c, j, o2 + a.R2);
+    tr = block_reduce(tr, red, false);
+    const double mu = tr / ((double)nx * nv);
+
+    // column sums of |Y - mu I| over the x column classes
+    int cls[6] = {0, 1, 2, nx - 3, nx - 2, nx - 1};
+    double best = 0.0;
+    for (int idx = t; idx < nv * 6; idx += kThreads) {
+        const int jp = idx / 6;
+        const int ip = cls[idx % 6];
+        if (ip < 0 || ip >= nx) continue;
+        double sum = 0.0;
+        const int R = max(a.R0, max(a.R1, a.R2));
+        for (int j = max(0, jp - R); j <= min(nv - 1, jp + R); ++j) {
+            const int b = jp - j;
+            const double a0 = (b >= -a.R0 && b <= a.R0) ? coeff(a, c, j, o0 + b + a.R0) : 0.0;
+            const double a1 = (b >= -a.R1 && b <= a.R1) ? coeff(a, c, j, o1 + b + a.R1) : 0.0;
+            const double a2 = (b >= -a.R2 && b <= a.R2) ? coeff(a, c, j, o2 + b + a.R2) : 0.0;
+            const double d0 = a0 - (b == 0 ? mu : 0.0);
+            if (ip - 2 >= 0) sum += fabs(a2);
+            if (ip - 1 >= 0) sum += fabs(a1);
+            sum += fabs(d0 + a2 * dt2_diag(ip, nx));
+            if (ip + 1 < nx) sum += fabs(a1);
+            if (ip + 2 < nx) sum += fabs(a2);
+        }
+        best = fmax(best, sum);
+        if (sum != sum) best = sum;   // keep NaN visible
+    }
+    const double norm = block_reduce(best, red, true);
+
+    if (t == 0) {
+        int s = 1, m = 0, flag = 0;
+        if (!isfinite(norm) || !isfinite(mu)) {
+            flag = MG_FLAG_NONFINITE;
+        } else if (norm > 0.0) {
+            const double* th = a.use24 ? kTheta24 : kTheta53;
+            long long bestc = -1;
+            for (int mm = 1; mm <= MG_THETA_MMAX; ++mm) {
+                double sd = ceil(norm / th[mm]);
+                if (sd > (double)kMaxS) continue;
+                long long ss = (long long)fmax(sd, 1.0);
+                long long cost = (long long)mm * ss;
+                if (bestc < 0 || cost < bestc) { bestc = cost; m = mm; s = (int)ss; }
+            }
+            if (bestc < 0) { flag = MG_FLAG_NORM; m = MG_THETA_MMAX; s = kMaxS; }
+        }
+        hdr[0] = s;
+        hdr[1] = m;
+        hdr[2] = flag;
+        double* tab = a.tables + pk * a.tstride;
+        int32_t* itab = reinterpret_cast<int32_t*>(tab);
+        itab[0] = s;                   // [0] s      (int32 in the first word)
+        itab[1] = 0;
+        itab[2] = m;                   // [1] m
+        itab[3] = 0;
+        tab[2] = flag == MG_FLAG_NONFINITE ? NAN : exp(mu / s);
+        tab[3] = mu;
+        tab[4] = norm;
+        itab[10] = flag;               // [5] flag
+        itab[11] = 0;
+        tab[6] = 0.0;
+        tab[7] = 0.0;
+    }
+    __syncthreads();
+    const double inv_s = 1.0 / hdr[0];
+    double* rows = a.tables + pk * a.tstride + MG_HDR;
+    for (int idx = t; idx < a.nv_pad * a.NBP; idx += kThreads) {
+        const int j = idx / a.NBP, e = idx % a.NBP;
+        double v = 0.0;
+        if (j < nv) {
+            v = coeff(a, c, j, e);
+            if (e == o0 + a.R0) v -= mu;
+        }
+        rows[idx] = v * inv_s;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int K, double tol,
+                           int precision, double* tables, hipStream_t s) {
+    (void)precision;
+    AsmArgs a;
+    a.basis = ops->basis_dev;
+    a.coef = coef;
+    a.tables = tables;
+    a.tstride = mg_table_stride(ops);
+    a.nx = ops->grid.nx;
+    a.nv = ops->grid.nv;
+    a.nv_pad = ops->nv_pad;
+    a.K = K;
+    a.NBP = ops->NBP;
+    a.nact = ops->nactive;
+    a.R0 = ops->R[0];
+    a.R1 = ops->R[1];
+    a.R2 = ops->R[2];
+    a.use24 = tol >= 0x1p-24 ? 1 : 0;
+    const int64_t blocks = P * K;
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
+    return hipGetLastError();
+}

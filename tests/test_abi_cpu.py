@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every entry point include/magnus.h
+declares; host-side argument checks run without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2207_09776_amd as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "magnus.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mg.LIB_PATH):
+        pytest.fail("libmagnus.so is not built (run python -m paper_2207_09776_amd.build)")
+    return mg.load_library()
+
+
+def test_header_declares_the_five_entry_points():
+    names = declared_functions()
+    for n in ("mg_build_operators", "mg_iterated_integrals", "mg_magnus_expmv", "mg_euler_step",
+              "mg_error_vs_exact"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(mg.EXPORTS) <= set(declared_functions())
+
+
+def test_version_and_error_string(lib):
+    assert b"gfx950" in lib.mg_version()
+    assert lib.mg_last_error() is not None
+
+
+def test_shape_checks_before_any_device_call(lib):
+    vp = ctypes.c_void_p
+    # Nf not a multiple of K
+    assert lib.mg_iterated_integrals(vp(8), 2, 100, 1.0, 3, 2, vp(8), None, None) == mg.MG_ESHAPE
+    assert b"multiple" in lib.mg_last_error()
+    # negative P, bad order, bad T
+    assert lib.mg_iterated_integrals(vp(8), -1, 96, 1.0, 3, 2, vp(8), None, None) == mg.MG_ESHAPE
+    assert lib.mg_iterated_integrals(vp(8), 2, 96, 1.0, 3, 4, vp(8), None, None) == mg.MG_EINVAL
+    assert lib.mg_iterated_integrals(vp(8), 2, 96, 0.0, 3, 2, vp(8), None, None) == mg.MG_EINVAL
+    # P = 0 is a no-op even with NULL buffers
+    assert lib.mg_iterated_integrals(None, 0, 96, 1.0, 3, 2, None, None, None) == mg.MG_OK
+    # NULL ops
+    assert lib.mg_magnus_expmv(None, None, 1, 1, None, 1, None, 0, 0.0, None, 0, None, None,
+                               None) == mg.MG_EINVAL
+    assert lib.mg_euler_step(None, None, 1, None, 1, 0.1, 0, None, 0, None, None) == mg.MG_EINVAL
+    assert lib.mg_workspace_bytes(None, 4, 4, 0) == 0
+
+
+def test_build_operators_argument_checks(lib):
+    g = mg.mg_grid(0, 8, -1.0, 1.0, -1.0, 1.0)
+    c = mg.mg_coeffs()
+    h = ctypes.c_void_p()
+    assert lib.mg_build_operators(ctypes.byref(g), ctypes.byref(c), 2, ctypes.byref(h)) == mg.MG_EINVAL
+    g = mg.mg_grid(8, 8, 1.0, -1.0, -1.0, 1.0)
+    assert lib.mg_build_operators(ctypes.byref(g), ctypes.byref(c), 2, ctypes.byref(h)) == mg.MG_EINVAL
+    g = mg.mg_grid(8, 8, -1.0, 1.0, -1.0, 1.0)
+    assert lib.mg_build_operators(ctypes.byref(g), ctypes.byref(c), 4, ctypes.byref(h)) == mg.MG_EINVAL
+    assert lib.mg_build_operators(None, ctypes.byref(c), 2, ctypes.byref(h)) == mg.MG_EINVAL
+
+
+def test_error_vs_exact_argument_checks(lib):
+    g = mg.mg_grid(8, 8, -1.0, 1.0, -1.0, 1.0)
+    ex = mg.mg_exact(1.0, 1.5, 0.25, 1.0)        # sigma^2 >= a: no closed form
+    vp = ctypes.c_void_p
+    assert lib.mg_error_vs_exact(ctypes.byref(g), ctypes.byref(ex), vp(8), vp(8), None, 1, 0,
+                                 vp(8), None) == mg.MG_EINVAL
+    ex = mg.mg_exact(1.0, 0.5, 0.25, 1.0)
+    assert lib.mg_error_vs_exact(ctypes.byref(g), ctypes.byref(ex), vp(8), vp(8), None, 1, 4,
+                                 vp(8), None) == mg.MG_EINVAL      # 8 >> 4 == 0: empty window
