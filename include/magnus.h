@@ -52,6 +52,8 @@ typedef int32_t mg_status;
 /* Per-path flag bits written to `flags[p]` (0 = path finished normally). */
 #define MG_FLAG_NONFINITE 1    /* a NaN or Inf appeared in the path's state   */
 #define MG_FLAG_NORM      2    /* ||Y_{p,k} - mu I||_1 exceeded the supported range */
+#define MG_FLAG_ABORT     4    /* a multi-workgroup launch gave up waiting for a
+                                  workgroup of its group (result not valid)    */
 
 /* Precision forms of the Taylor chain (the state u is FP64 in both). */
 #define MG_FP64  0             /* every operation in FP64                     */
@@ -99,9 +101,9 @@ typedef struct mg_ops mg_ops;
  *                  mg_free_operators.  The handle is immutable after build and
  *                  may be used from several streams at once.
  * Errors: MG_EINVAL (NULL, order outside 1..3, nx or nv < 1, empty domain),
- *         MG_EUNSUPPORTED (coefficients outside the supported set, nx > 128
- *         and nv > 1024 combinations this build has no kernel for),
- *         MG_EHIP, MG_ENOMEM.
+ *         MG_EUNSUPPORTED (coefficients outside the supported set),
+ *         MG_EHIP, MG_ENOMEM.  Grid sizes without a kernel are reported by
+ *         the compute calls.
  * ------------------------------------------------------------------------ */
 mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32_t order,
                              mg_ops** out);

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmagnus.so")
 
 MG_OK, MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP, MG_ENOMEM = 0, -1, -2, -3, -4, -5
-MG_FLAG_NONFINITE, MG_FLAG_NORM = 1, 2
+MG_FLAG_NONFINITE, MG_FLAG_NORM, MG_FLAG_ABORT = 1, 2, 4
 MG_FP64, MG_FP32C = 0, 1
 PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmagnus.so")
 
 SOURCES = ["api.hip", "ops_build.cpp", "integrals.hip", "assemble.hip", "expmv_resident.hip",
-           "error.hip"]
+           "expmv_coop.hip", "error.hip"]
 
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

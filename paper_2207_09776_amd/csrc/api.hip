@@ -137,10 +137,27 @@ mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t N
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_euler_increments");
 }
 
+namespace {
+// Kernel family for a grid: resident (one workgroup per path) or cooperative.
+enum class Family { None, Resident, Coop };
+Family family_of(const mg_ops* ops, int precision) {
+    if (launch_expmv_resident(ops, nullptr, 0, 1, 1, nullptr, 0, nullptr, 0.0, precision, nullptr,
+                              nullptr, nullptr, true) == hipSuccess)
+        return Family::Resident;
+    if (coop_rows_per_group_member(ops->grid.nx) > 0) return Family::Coop;
+    return Family::None;
+}
+}  // namespace
+
 size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t precision) {
-    (void)precision;
-    if (!ops || P <= 0 || K <= 0) return 0;
-    return (size_t)P * (size_t)K * mg_table_stride(ops) * sizeof(double);
+    if (!ops || P <= 0 || K <= 0 || (precision != MG_FP64 && precision != MG_FP32C)) return 0;
+    size_t bytes = (size_t)P * (size_t)K * mg_table_bytes(ops, precision);
+    if (family_of(ops, precision) == Family::Coop) {
+        CoopPlan plan;
+        if (coop_plan(ops, precision, P, &plan) != hipSuccess) return 0;
+        bytes += plan.bytes;
+    }
+    return bytes;
 }
 
 mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
@@ -153,25 +170,39 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
     if (P > 0x7fffffff / (int64_t)K) return mg_fail(MG_ESHAPE, "mg_magnus_expmv: P*K too large");
     if (precision != MG_FP64 && precision != MG_FP32C)
         return mg_fail(MG_EINVAL, "mg_magnus_expmv: unknown precision");
-    if (precision == MG_FP32C)
-        return mg_fail(MG_EUNSUPPORTED, "mg_magnus_expmv: MG_FP32C is not built yet");
     if (!(tol == tol) || tol >= 1.0) return mg_fail(MG_EINVAL, "mg_magnus_expmv: tol must be < 1");
     if (tol <= 0.0) tol = precision == MG_FP64 ? 0x1p-53 : 0x1p-24;
     hipStream_t s = (hipStream_t)stream;
-    if (launch_expmv_resident(ops, nullptr, P, K, nullptr, 0, nullptr, tol, nullptr, nullptr, s,
-                              true) != hipSuccess)
+    const Family fam = family_of(ops, precision);
+    if (fam == Family::None)
         return mg_fail(MG_EUNSUPPORTED, "mg_magnus_expmv: no kernel for this grid size");
     if (P == 0) return MG_OK;
     if (!coef || !u0 || !uT || !ws) return mg_fail(MG_EINVAL, "mg_magnus_expmv: NULL pointer");
-    const size_t need = mg_workspace_bytes(ops, P, K, precision);
+    CoopPlan plan;
+    if (fam == Family::Coop) {
+        hipError_t e = coop_plan(ops, precision, P, &plan);
+        if (e != hipSuccess)
+            return mg_fail(MG_EUNSUPPORTED,
+                           std::string("mg_magnus_expmv: no cooperative plan: ") +
+                               hipGetErrorString(e) + " (stage " + std::to_string(plan.stage) +
+                               ", G " + std::to_string(plan.G) + ", per_cu " +
+                               std::to_string(plan.per_cu) + ", cus " + std::to_string(plan.cus) +
+                               ", lds " + std::to_string(plan.lds) + ")");
+    }
+    const size_t tbytes = mg_table_bytes(ops, precision);
+    const size_t need = (size_t)P * K * tbytes + (fam == Family::Coop ? plan.bytes : 0);
     if (ws_bytes < need)
         return mg_fail(MG_ENOMEM, "mg_magnus_expmv: workspace smaller than mg_workspace_bytes()");
-    double* tables = (double*)ws;
+    char* tables = (char*)ws;
     hipError_t e = launch_assemble(ops, coef, P, K, tol, precision, tables, s);
     if (e != hipSuccess) return hip_fail(e, "mg_magnus_expmv (assemble)");
     TimingScope ts("expmv", s);
-    e = launch_expmv_resident(ops, tables, P, K, u0, u0_broadcast, uT, tol, stats, flags, s,
-                              false);
+    if (fam == Family::Resident)
+        e = launch_expmv_resident(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, tol, precision,
+                                  stats, flags, s, false);
+    else
+        e = launch_expmv_coop(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, tol, precision,
+                              stats, flags, tables + (size_t)P * K * tbytes, plan, s);
     ts.done();
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_magnus_expmv");
 }

@@ -7,7 +7,8 @@
 // from the factored form, and (m, s) minimise m * s subject to
 // ||Y - mu I||_1 / s <= theta_m (truncated-Taylor thresholds of Al-Mohy and
 // Higham for the requested tolerance).  The table written for (p, k) holds the
-// header (s, m, exp(mu/s), mu, norm, flag) and the rows of (Y - mu I)/s.
+// header (s, m, exp(mu/s), mu, norm, flag) and the rows of (Y - mu I)/s, in
+// FP64, or rounded once to FP32 for the compensated FP32 form.
 //
 // Column sums.  With M = sum_q V_q (x) Dt^q (Dt = tridiag(-1,0,1)), column
 // (i', j') of Y - mu I has entries in rows (i, j), |j - j'| <= R, i - i' in
@@ -29,8 +30,9 @@ constexpr int kMaxS = 1 << 14;   // beyond this the path is flagged (MG_FLAG_NOR
 struct AsmArgs {
     const double* basis;       // [6][nv][NBP]
     const double* coef;        // [P][K][6]
-    double* tables;            // [P][K][tstride]
-    size_t tstride;
+    char* tables;              // [P][K] records of tbytes
+    size_t tbytes;
+    int f32;                   // rows in FP32 (compensated form) instead of FP64
     int nx, nv, nv_pad, K, NBP, nact;
     int R0, R1, R2;
     int use24;                 // theta table for 2^-24 instead of 2^-53
@@ -124,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
         hdr[0] = s;
         hdr[1] = m;
         hdr[2] = flag;
-        double* tab = a.tables + pk * a.tstride;
+        double* tab = reinterpret_cast<double*>(a.tables + pk * a.tbytes);
         int32_t* itab = reinterpret_cast<int32_t*>(tab);
         itab[0] = s;                   // [0] s      (int32 in the first word)
         itab[1] = 0;
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
     }
     __syncthreads();
     const double inv_s = 1.0 / hdr[0];
-    double* rows = a.tables + pk * a.tstride + MG_HDR;
+    char* rows = a.tables + pk * a.tbytes + 64;
     for (int idx = t; idx < a.nv_pad * a.NBP; idx += kThreads) {
         const int j = idx / a.NBP, e = idx % a.NBP;
         double v = 0.0;
@@ -148,20 +150,23 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
             v = coeff(a, c, j, e);
             if (e == o0 + a.R0) v -= mu;
         }
-        rows[idx] = v * inv_s;
+        if (a.f32)
+            reinterpret_cast<float*>(rows)[idx] = (float)(v * inv_s);
+        else
+            reinterpret_cast<double*>(rows)[idx] = v * inv_s;
     }
 }
 
 }  // namespace
 
 hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int K, double tol,
-                           int precision, double* tables, hipStream_t s) {
-    (void)precision;
+                           int precision, char* tables, hipStream_t s) {
     AsmArgs a;
     a.basis = ops->basis_dev;
     a.coef = coef;
     a.tables = tables;
-    a.tstride = mg_table_stride(ops);
+    a.tbytes = mg_table_bytes(ops, precision);
+    a.f32 = precision == MG_FP32C ? 1 : 0;
     a.nx = ops->grid.nx;
     a.nv = ops->grid.nv;
     a.nv_pad = ops->nv_pad;

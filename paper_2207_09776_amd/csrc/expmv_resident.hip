@@ -1,11 +1,11 @@
-// Register-resident Taylor chain of the iterated Magnus scheme, and the
-// Euler-Maruyama baseline, for grids whose per-path state fits on one
-// workgroup (nx <= 128, nv <= 128).
+// Register-resident Taylor chain of the iterated Magnus scheme (FP64 and the
+// compensated FP32 form) and the Euler-Maruyama baseline, for grids whose
+// per-path state fits on one workgroup (nx <= 128, nv <= 128).
 //
 // Work decomposition (one workgroup = one path, all K Magnus steps):
 //   lane l of every wave owns the PX consecutive x points l*PX .. l*PX+PX-1;
 //   wave w owns the RJ consecutive v rows w*RJ .. w*RJ+RJ-1.
-// The Taylor term d, the partial sum F (which is also the state u between
+// The Taylor term and the partial sum (which is also the state u between
 // sub-steps) stay in VGPRs for the whole launch; HBM is touched only to read
 // u0 and the per-step coefficient tables and to write uT.
 //
@@ -21,204 +21,38 @@
 // exchange; the same barrier publishes the per-wave inf-norms used by the
 // early-termination test of the Taylor sum.
 //
-// Taylor step (FP64): with Y' = (Y - mu I)/s from the table, the chain is kept
-// unscaled, d_j = Y'^j u, and F = sum_j d_j / j!; after each of the s
-// sub-steps u <- exp(mu/s) F.  The sum stops after term j when
-// ||c_{j-1}||_inf + ||c_j||_inf <= tol ||F||_inf with c_j = d_j / j!.
+// FP64 chain: with Y' = (Y - mu I)/s from the table, the chain is kept
+// unscaled, d_j = Y'^j u, and F = sum_j d_j / j!; after each of the s sub-steps
+// u <- exp(mu/s) F.
+// FP32 compensated chain: c_j = Y' c_{j-1} / j in FP32 (FP32 tables), the sum
+// F = hi + lo is accumulated with Kahan compensation in FP32; at the end of a
+// sub-step u = exp(mu/s) (hi + lo) is formed in FP64 and split again, so the
+// state between sub-steps and Magnus steps keeps ~48 significant bits.
+// Both stop a sub-step after term j when
+// ||c_{j-1}||_inf + ||c_j||_inf <= tol ||F||_inf.
 
 #include <cmath>
 
-#include "mg_internal.h"
+#include "kernel_common.h"
 
 namespace {
 
-// ---- DPP helpers: whole-wave shifts by one lane, zero fill ----------------
-// wave_shr:1 (lane l receives lane l-1) and wave_shl:1 (lane l receives l+1).
-__device__ inline double from_left(double x) {
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-__device__ inline double from_right(double x) {
-    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, true);
-    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, true);
-    return __hiloint2double(hi, lo);
-}
-
-// Dt y at this lane's PX points: y[q+1] - y[q-1] with neighbours from the
-// adjacent lanes (zero beyond the wave, which is the zero boundary).
-template <int PX>
-__device__ inline void dt_apply(const double (&y)[PX], double (&out)[PX]) {
-    const double left = from_left(y[PX - 1]);
-    const double right = from_right(y[0]);
-#pragma unroll
-    for (int q = 0; q < PX; ++q) {
-        const double a = (q + 1 < PX) ? y[q + 1] : right;
-        const double b = (q > 0) ? y[q - 1] : left;
-        out[q] = a - b;
-    }
-}
-
-// max(acc, |x|) as one v_max_f64 with an abs source modifier (fmax() adds an
-// IEEE canonicalisation per operand).  NaN inputs may be dropped; non-finite
-// states are detected separately at the end of the launch.
-__device__ inline double max_abs(double acc, double x) {
-    double r;
-    asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(acc), "v"(x));
-    return r;
-}
-
-__device__ inline double wave_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = max_abs(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Wave-uniform copy of a value every lane holds identically.
-__device__ inline double uniform(double x) {
-    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
-    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
-    return __hiloint2double(hi, lo);
-}
-
-template <int R0, int R1, int R2>
-struct Bands {
-    static constexpr int RH = (R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2));
-    static constexpr int O1 = 2 * R0 + 1;
-    static constexpr int O2 = O1 + 2 * R1 + 1;
-};
-
-// One application of the banded-Kronecker operator to the RJ rows of this
-// wave.  `din(rr)` yields the input row rr in [-RH, RJ + RH).  `coef(r, e)` is
-// the coefficient e of local row r; rows beyond nv have zero coefficients in
-// the (padded) tables, so they produce zeros without a branch.  QMAX is the
-// highest power of Dt present.
-template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, class In, class Coef>
-__device__ inline void apply_operator(In din, Coef coef, int lane, int nx,
-                                      double (&out)[RJ][PX]) {
-    using BD = Bands<R0, R1, R2>;
-    constexpr int NB = BD::O2 + 2 * R2 + 1;
-    // coefficients of the current row; the next row's are loaded while the
-    // current one is computed (scheduling barriers keep the scalar loads from
-    // being hoisted all at once)
-    double cur[NB], nxt[NB];
-#pragma unroll
-    for (int e = 0; e < NB; ++e) cur[e] = coef(0, e);
-#pragma unroll
-    for (int r = 0; r < RJ; ++r) {
-        if (r + 1 < RJ) {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) nxt[e] = coef(r + 1, e);
-        }
-        {
-            double y0[PX], y1[PX], y2[PX];
-#pragma unroll
-            for (int q = 0; q < PX; ++q) y0[q] = y1[q] = y2[q] = 0.0;
-#pragma unroll
-            for (int b = -R0; b <= R0; ++b)
-#pragma unroll
-                for (int q = 0; q < PX; ++q) y0[q] = fma(cur[b + R0], din(r + b, q), y0[q]);
-            if (QMAX >= 1) {
-#pragma unroll
-                for (int b = -R1; b <= R1; ++b)
-#pragma unroll
-                    for (int q = 0; q < PX; ++q)
-                        y1[q] = fma(cur[BD::O1 + b + R1], din(r + b, q), y1[q]);
-            }
-            if (QMAX >= 2) {
-#pragma unroll
-                for (int b = -R2; b <= R2; ++b)
-#pragma unroll
-                    for (int q = 0; q < PX; ++q)
-                        y2[q] = fma(cur[BD::O2 + b + R2], din(r + b, q), y2[q]);
-                double t[PX];
-                dt_apply<PX>(y2, t);
-#pragma unroll
-                for (int q = 0; q < PX; ++q) {
-                    y1[q] += t[q];
-                    // the inner Dt result lives on the grid only (truncated product)
-                    if (!FULLX && lane * PX + q >= nx) y1[q] = 0.0;
-                }
-            }
-            if (QMAX >= 1) {
-                double t[PX];
-                dt_apply<PX>(y1, t);
-#pragma unroll
-                for (int q = 0; q < PX; ++q) y0[q] += t[q];
-            }
-#pragma unroll
-            for (int q = 0; q < PX; ++q)
-                out[r][q] = (!FULLX && lane * PX + q >= nx) ? 0.0 : y0[q];
-        }
-        if (r + 1 < RJ) {
-#pragma unroll
-            for (int e = 0; e < NB; ++e) cur[e] = nxt[e];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-// LDS halo layout: halo[parity][wave + 1][slot][64*PX] for waves -1 .. NW; the
-// guard waves -1 and NW are zero rows (the zero boundary in v) so that every
-// fetch is unconditional.  Slots 0..RH-1 hold a wave's first RH rows, slots
-// RH..2RH-1 its last RH rows.
-template <int PX, int RJ, int NW, int RH>
-struct Halo {
-    double* base;
-    __device__ double* slot(int par, int w, int s) const {
-        return base + (((size_t)par * (NW + 2) + (w + 1)) * (2 * RH) + s) * (64 * PX);
-    }
-    __device__ void zero_guards(int tid, int nthreads) const {
-        for (int par = 0; par < 2; ++par)
-            for (int g = 0; g < 2; ++g) {
-                double* p = slot(par, g == 0 ? -1 : NW, 0);
-                for (int i = tid; i < 2 * RH * 64 * PX; i += nthreads) p[i] = 0.0;
-            }
-    }
-    __device__ void publish(int par, int w, int lane, const double (&d)[RJ][PX]) const {
-#pragma unroll
-        for (int s = 0; s < RH; ++s) {
-            double* top = slot(par, w, s) + lane * PX;
-            double* bot = slot(par, w, RH + s) + lane * PX;
-#pragma unroll
-            for (int q = 0; q < PX; ++q) {
-                top[q] = d[s][q];
-                bot[q] = d[RJ - RH + s][q];
-            }
-        }
-    }
-    // rows -RH..-1 (from wave w-1) and RJ..RJ+RH-1 (from wave w+1)
-    __device__ void fetch(int par, int w, int lane, double (&top)[RH][PX],
-                          double (&bot)[RH][PX]) const {
-#pragma unroll
-        for (int s = 0; s < RH; ++s) {
-#pragma unroll
-            for (int q = 0; q < PX; ++q) {
-                top[s][q] = slot(par, w - 1, RH + s)[lane * PX + q];
-                bot[s][q] = slot(par, w + 1, s)[lane * PX + q];
-            }
-        }
-    }
-};
-
-template <int PX, int RJ, int NW, int R0, int R1, int R2>
-constexpr size_t resident_lds_bytes() {
-    constexpr int RH = Bands<R0, R1, R2>::RH;
-    return (size_t)2 * (NW + 2) * 2 * (RH > 0 ? RH : 1) * 64 * PX * sizeof(double) +
-           (size_t)2 * NW * 2 * sizeof(double) + 2 * NW * sizeof(double) + 16;
-}
+using namespace mgk;
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
-    const double* __restrict__ tables, size_t tstride, int K, int nx, int nv,
+    const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, double tol,
     int32_t* __restrict__ stats, int32_t* __restrict__ flags) {
+    using T = double;
     using BD = Bands<R0, R1, R2>;
     constexpr int RH = BD::RH > 0 ? BD::RH : 1;
-    constexpr int NBP = ((2 * R0 + 1) + (2 * R1 + 1) + (2 * R2 + 1) + 1) & ~1;
-    extern __shared__ double lds[];
-    Halo<PX, RJ, NW, RH> halo{lds};
-    double* red = lds + (size_t)2 * (NW + 2) * 2 * RH * 64 * PX;     // [2][NW][2]
-    double* red2 = red + 2 * NW * 2;                            // [2][NW]
+    constexpr int NBP = BD::NBP;
+    extern __shared__ double lds_d[];
+    T* lds = reinterpret_cast<T*>(lds_d);
+    Halo<PX, RJ, NW, RH, T> halo{lds};
+    T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);   // [2][NW][2]
+    T* red2 = red + 2 * NW * 2;                                 // [2][NW]
     int* sflag = reinterpret_cast<int*>(red2 + 2 * NW);
 
     const int lane = threadIdx.x & 63;
@@ -230,7 +64,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     if (threadIdx.x == 0) *sflag = 0;
     halo.zero_guards(threadIdx.x, 64 * NW);
 
-    double F[RJ][PX];
+    T F[RJ][PX];
     {
         const double* src = u0 + (u0_bcast ? 0 : (size_t)p * N);
 #pragma unroll
@@ -242,8 +76,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
             }
     }
     // ||u||_inf of the state (per-wave partial, LDS, barrier)
-    auto state_norm = [&](int par2) -> double {
-        double m = 0.0;
+    auto state_norm = [&](int par2) -> T {
+        T m = 0;
 #pragma unroll
         for (int r = 0; r < RJ; ++r)
 #pragma unroll
@@ -251,42 +85,41 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
         m = wave_max(m);
         if (lane == 0) red2[par2 * NW + w] = m;
         __syncthreads();
-        double g = 0.0;
+        T g = 0;
         for (int i = 0; i < NW; ++i) g = max_abs(g, red2[par2 * NW + i]);
         return uniform(g);
     };
 
-    int sub_par = 0;                 // parity of red2 use
-    double unorm = state_norm(sub_par);
+    int sub_par = 0;
+    T unorm = state_norm(sub_par);
     sub_par ^= 1;
-    int tpar = 0;                    // parity of the per-term halo/red buffers
+    int tpar = 0;
     int pflag = 0;
 
     for (int k = 0; k < K; ++k) {
-        const double* tab = tables + ((size_t)p * K + k) * tstride;
-        const int32_t* itab = reinterpret_cast<const int32_t*>(tab);
-        const int s = itab[0];
-        const int m = itab[2];
-        const double es = tab[2];
-        pflag |= itab[10];
-        const double* rows = tab + MG_HDR + (size_t)row0 * NBP;
-        auto coef = [&](int r, int e) -> double { return rows[r * NBP + e]; };
+        const TableView tv{tables + ((size_t)p * K + k) * tbytes};
+        const int s = tv.s();
+        const int m = tv.m();
+        const double es = tv.es();
+        pflag |= tv.flag();
+        const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
+        auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
         int terms = 0;
         for (int sub = 0; sub < s; ++sub) {
-            double d[RJ][PX];
+            T d[RJ][PX];
 #pragma unroll
             for (int r = 0; r < RJ; ++r)
 #pragma unroll
                 for (int q = 0; q < PX; ++q) d[r][q] = F[r][q];
-            double c1 = unorm;
-            double fj = 1.0;
+            T c1 = unorm;
+            T fj = 1;
             for (int j = 1; j <= m; ++j) {
                 halo.publish(tpar, w, lane, d);
                 __syncthreads();
                 if (j > 1) {
                     // norms of term j-1, published before this barrier
-                    double c2 = 0.0, fn = 0.0;
-                    const double* rr = red + (size_t)(tpar ^ 1) * NW * 2;
+                    T c2 = 0, fn = 0;
+                    const T* rr = red + (size_t)(tpar ^ 1) * NW * 2;
                     for (int i = 0; i < NW; ++i) {
                         c2 = max_abs(c2, rr[2 * i]);
                         fn = max_abs(fn, rr[2 * i + 1]);
@@ -296,17 +129,17 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                     if (c1 + c2 <= tol * fn) break;
                     c1 = c2;
                 }
-                double top[RH][PX], bot[RH][PX];
+                T top[RH][PX], bot[RH][PX];
                 halo.fetch(tpar, w, lane, top, bot);
-                auto din = [&](int rr, int q) -> double {
+                auto din = [&](int rr, int q) -> T {
                     if (rr < 0) return top[rr + RH][q];
                     if (rr >= RJ) return bot[rr - RJ][q];
                     return d[rr][q];
                 };
-                double dn[RJ][PX];
-                apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX>(din, coef, lane, nx, dn);
-                fj /= (double)j;             // 1/j!
-                double mc = 0.0, mf = 0.0;
+                T dn[RJ][PX];
+                apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX, T>(din, coef, lane, nx, dn);
+                fj /= (T)j;             // 1/j!
+                T mc = 0, mf = 0;
 #pragma unroll
                 for (int r = 0; r < RJ; ++r)
 #pragma unroll
@@ -355,17 +188,22 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     if (flags && threadIdx.x == 0) flags[p] = *sflag | pflag;
 }
 
-// Euler-Maruyama: u <- u + (dt B + dW_n A) u for n = 0..NE-1.
+// Compensated FP32 form (see the file header).
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
-__global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
-    const double* __restrict__ basis, int nx, int nv, int nv_pad, double* __restrict__ u,
-    const double* __restrict__ dWE, int NE, double dt, int32_t* __restrict__ flags) {
+__global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
+    const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
+    const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, float tol,
+    int32_t* __restrict__ stats, int32_t* __restrict__ flags) {
+    using T = float;
     using BD = Bands<R0, R1, R2>;
     constexpr int RH = BD::RH > 0 ? BD::RH : 1;
-    constexpr int NBP = ((2 * R0 + 1) + (2 * R1 + 1) + (2 * R2 + 1) + 1) & ~1;
-    extern __shared__ double lds[];
-    Halo<PX, RJ, NW, RH> halo{lds};
-    int* sflag = reinterpret_cast<int*>(lds + (size_t)2 * (NW + 2) * 2 * RH * 64 * PX);
+    constexpr int NBP = BD::NBP;
+    extern __shared__ double lds_d[];
+    T* lds = reinterpret_cast<T*>(lds_d);
+    Halo<PX, RJ, NW, RH, T> halo{lds};
+    T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);
+    T* red2 = red + 2 * NW * 2;
+    int* sflag = reinterpret_cast<int*>(red2 + 2 * NW);
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -376,7 +214,164 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     if (threadIdx.x == 0) *sflag = 0;
     halo.zero_guards(threadIdx.x, 64 * NW);
 
-    double d[RJ][PX];
+    // F = hi + lo (hi carries the FP32 value, lo the compensation)
+    T hi[RJ][PX], lo[RJ][PX];
+    {
+        const double* src = u0 + (u0_bcast ? 0 : (size_t)p * N);
+#pragma unroll
+        for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                const int i = lane * PX + q;
+                const double u = (r < nrows && i < nx) ? src[(size_t)(row0 + r) * nx + i] : 0.0;
+                hi[r][q] = (float)u;
+                lo[r][q] = (float)(u - (double)hi[r][q]);
+            }
+    }
+    auto state_norm = [&](int par2) -> T {
+        T m = 0;
+#pragma unroll
+        for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) m = max_abs(m, hi[r][q]);
+        m = wave_max(m);
+        if (lane == 0) red2[par2 * NW + w] = m;
+        __syncthreads();
+        T g = 0;
+        for (int i = 0; i < NW; ++i) g = max_abs(g, red2[par2 * NW + i]);
+        return uniform(g);
+    };
+
+    int sub_par = 0;
+    T unorm = state_norm(sub_par);
+    sub_par ^= 1;
+    int tpar = 0;
+    int pflag = 0;
+
+    for (int k = 0; k < K; ++k) {
+        const TableView tv{tables + ((size_t)p * K + k) * tbytes};
+        const int s = tv.s();
+        const int m = tv.m();
+        const double es = tv.es();
+        pflag |= tv.flag();
+        const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
+        auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
+        int terms = 0;
+        for (int sub = 0; sub < s; ++sub) {
+            T c[RJ][PX];
+#pragma unroll
+            for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                for (int q = 0; q < PX; ++q) c[r][q] = hi[r][q];
+            T c1 = unorm;
+            for (int j = 1; j <= m; ++j) {
+                halo.publish(tpar, w, lane, c);
+                __syncthreads();
+                if (j > 1) {
+                    T c2 = 0, fn = 0;
+                    const T* rr = red + (size_t)(tpar ^ 1) * NW * 2;
+                    for (int i = 0; i < NW; ++i) {
+                        c2 = max_abs(c2, rr[2 * i]);
+                        fn = max_abs(fn, rr[2 * i + 1]);
+                    }
+                    c2 = uniform(c2);
+                    fn = uniform(fn);
+                    if (c1 + c2 <= tol * fn) break;
+                    c1 = c2;
+                }
+                T top[RH][PX], bot[RH][PX];
+                halo.fetch(tpar, w, lane, top, bot);
+                auto din = [&](int rr, int q) -> T {
+                    if (rr < 0) return top[rr + RH][q];
+                    if (rr >= RJ) return bot[rr - RJ][q];
+                    return c[rr][q];
+                };
+                T cn[RJ][PX];
+                apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX, T>(din, coef, lane, nx, cn);
+                const T invj = uniform((float)(1.0 / (double)j));
+                T mc = 0, mf = 0;
+#pragma unroll
+                for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                    for (int q = 0; q < PX; ++q) {
+                        const T x = cn[r][q] * invj;
+                        c[r][q] = x;
+                        // Kahan: F = hi + lo gains x
+                        const T y = x + lo[r][q];
+                        const T t = hi[r][q] + y;
+                        lo[r][q] = y - (t - hi[r][q]);
+                        hi[r][q] = t;
+                        mc = max_abs(mc, x);
+                        mf = max_abs(mf, t);
+                    }
+                mc = wave_max(mc);
+                mf = wave_max(mf);
+                if (lane == 0) {
+                    red[(size_t)tpar * NW * 2 + 2 * w] = mc;
+                    red[(size_t)tpar * NW * 2 + 2 * w + 1] = mf;
+                }
+                tpar ^= 1;
+                ++terms;
+            }
+            // u = exp(mu/s) (hi + lo) in FP64, split again
+#pragma unroll
+            for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                for (int q = 0; q < PX; ++q) {
+                    const double u = es * ((double)hi[r][q] + (double)lo[r][q]);
+                    hi[r][q] = (float)u;
+                    lo[r][q] = (float)(u - (double)hi[r][q]);
+                }
+            unorm = state_norm(sub_par);
+            sub_par ^= 1;
+        }
+        if (stats && threadIdx.x == 0) {
+            stats[((size_t)p * K + k) * 2] = terms;
+            stats[((size_t)p * K + k) * 2 + 1] = s;
+        }
+    }
+
+    bool bad = false;
+    double* dst = uT + (size_t)p * N;
+#pragma unroll
+    for (int r = 0; r < RJ; ++r)
+#pragma unroll
+        for (int q = 0; q < PX; ++q) {
+            const int i = lane * PX + q;
+            if (r < nrows && i < nx) {
+                const double u = (double)hi[r][q] + (double)lo[r][q];
+                dst[(size_t)(row0 + r) * nx + i] = u;
+                bad |= !isfinite(u);
+            }
+        }
+    if (bad) atomicOr(sflag, MG_FLAG_NONFINITE);
+    __syncthreads();
+    if (flags && threadIdx.x == 0) flags[p] = *sflag | pflag;
+}
+
+// Euler-Maruyama: u <- u + (dt B + dW_n A) u for n = 0..NE-1 (FP64).
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
+__global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
+    const double* __restrict__ basis, int nx, int nv, int nv_pad, double* __restrict__ u,
+    const double* __restrict__ dWE, int NE, double dt, int32_t* __restrict__ flags) {
+    using T = double;
+    using BD = Bands<R0, R1, R2>;
+    constexpr int RH = BD::RH > 0 ? BD::RH : 1;
+    constexpr int NBP = BD::NBP;
+    extern __shared__ double lds[];
+    Halo<PX, RJ, NW, RH, T> halo{lds};
+    int* sflag = reinterpret_cast<int*>(lds + halo_bytes<PX, NW, RH, T>() / sizeof(T));
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t p = blockIdx.x;
+    const int row0 = w * RJ;
+    const int nrows = min(RJ, max(0, nv - row0));
+    const size_t N = (size_t)nx * nv;
+    if (threadIdx.x == 0) *sflag = 0;
+    halo.zero_guards(threadIdx.x, 64 * NW);
+
+    T d[RJ][PX];
     double* src = u + (size_t)p * N;
 #pragma unroll
     for (int r = 0; r < RJ; ++r)
@@ -391,20 +386,20 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     int tpar = 0;
     for (int n = 0; n < NE; ++n) {
         const double wn = dw[n];
-        auto coef = [&](int r, int e) -> double {
+        auto coef = [&](int r, int e) -> T {
             return fma(dt, Brows[r * NBP + e], wn * Arows[r * NBP + e]);
         };
         halo.publish(tpar, w, lane, d);
         __syncthreads();
-        double top[RH][PX], bot[RH][PX];
+        T top[RH][PX], bot[RH][PX];
         halo.fetch(tpar, w, lane, top, bot);
-        auto din = [&](int rr, int q) -> double {
+        auto din = [&](int rr, int q) -> T {
             if (rr < 0) return top[rr + RH][q];
             if (rr >= RJ) return bot[rr - RJ][q];
             return d[rr][q];
         };
-        double dn[RJ][PX];
-        apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX>(din, coef, lane, nx, dn);
+        T dn[RJ][PX];
+        apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX, T>(din, coef, lane, nx, dn);
 #pragma unroll
         for (int r = 0; r < RJ; ++r)
 #pragma unroll
@@ -450,23 +445,33 @@ bool pick_shape(int nx, int nv, Shape& sh) {
 }
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
-hipError_t run_expmv(const mg_ops* ops, const double* tables, int64_t P, int K, const double* u0,
-                     int bc, double* uT, double tol, int32_t* stats, int32_t* flags,
-                     hipStream_t s) {
-    constexpr size_t lds = resident_lds_bytes<PX, RJ, NW, R0, R1, R2>();
-    auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
-    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables,
-                       mg_table_stride(ops), K, ops->grid.nx, ops->grid.nv, u0, bc, uT, tol,
-                       stats, flags);
+hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P, int K,
+                     const double* u0, int bc, double* uT, double tol, int precision,
+                     int32_t* stats, int32_t* flags, hipStream_t s) {
+    constexpr int RH = Bands<R0, R1, R2>::RH > 0 ? Bands<R0, R1, R2>::RH : 1;
+    if (precision == MG_FP64) {
+        constexpr size_t lds = resident_lds_bytes<PX, NW, RH, double>();
+        auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables, tbytes, K,
+                           ops->grid.nx, ops->grid.nv, u0, bc, uT, tol, stats, flags);
+    } else {
+        constexpr size_t lds = resident_lds_bytes<PX, NW, RH, float>();
+        auto kern = expmv_resident_f32c_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
+        (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)lds);
+        hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables, tbytes, K,
+                           ops->grid.nx, ops->grid.nv, u0, bc, uT, (float)tol, stats, flags);
+    }
     return hipGetLastError();
 }
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
 hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE, int NE,
                      double dt, int32_t* flags, hipStream_t s) {
-    constexpr size_t lds = resident_lds_bytes<PX, RJ, NW, R0, R1, R2>();
+    constexpr int RH = Bands<R0, R1, R2>::RH > 0 ? Bands<R0, R1, R2>::RH : 1;
+    constexpr size_t lds = halo_bytes<PX, NW, RH, double>() + 16;
     auto kern = euler_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
@@ -479,12 +484,23 @@ hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE,
 // host builder rounds to: (1,0,0,1) and (2,1,0,1) cover orders 1 and 2 of the
 // constant-coefficient Langevin operator, (2,1,1,2) its order 3, (3,3,3,2)
 // v-dependent coefficients.  B and A (Euler) only carry Dt^0 and Dt^1.
-#define MG_FOR_SHAPE(PX, RJ, NW, FULLX, CALL)                                              \
+#define MG_FOR_SHAPE(PX, RJ, NW, FULLX, CALL)                                                  \
     if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX); \
     if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX); \
     return hipErrorInvalidValue;
+
+#define MG_DISPATCH(CALL)                                                                      \
+    {                                                                                          \
+        const bool full = (nx == 64 * sh.PX);                                                  \
+        if (sh.PX == 1 && sh.NW == 2) { if (full) { MG_FOR_SHAPE(1, 16, 2, true, CALL) } else { MG_FOR_SHAPE(1, 16, 2, false, CALL) } } \
+        if (sh.PX == 1 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(1, 16, 4, true, CALL) } else { MG_FOR_SHAPE(1, 16, 4, false, CALL) } } \
+        if (sh.PX == 1 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(1, 16, 8, true, CALL) } else { MG_FOR_SHAPE(1, 16, 8, false, CALL) } } \
+        if (sh.PX == 2 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(2, 16, 4, true, CALL) } else { MG_FOR_SHAPE(2, 16, 4, false, CALL) } } \
+        if (sh.PX == 2 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(2, 16, 8, true, CALL) } else { MG_FOR_SHAPE(2, 16, 8, false, CALL) } } \
+        return hipErrorInvalidValue;                                                           \
+    }
 
 }  // namespace
 
@@ -493,27 +509,21 @@ int resident_rows(int nx, int nv) {
     return pick_shape(nx, nv, sh) ? sh.NW * sh.RJ : 0;
 }
 
-hipError_t launch_expmv_resident(const mg_ops* ops, const double* tables, int64_t P, int K,
-                                 const double* u0, int u0_broadcast, double* uT, double tol,
-                                 int32_t* stats, int32_t* flags, hipStream_t s, bool dry_run) {
+hipError_t launch_expmv_resident(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
+                                 int K, const double* u0, int u0_broadcast, double* uT, double tol,
+                                 int precision, int32_t* stats, int32_t* flags, hipStream_t s,
+                                 bool dry_run) {
     Shape sh;
     const int nx = ops->grid.nx, nv = ops->grid.nv;
     if (!pick_shape(nx, nv, sh)) return hipErrorInvalidValue;
     if (dry_run) return hipSuccess;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-    // The band shapes must match the table layout exactly (NBP is derived from
-    // R), so the instantiation is chosen by the exact radii.
-#define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX) \
-    run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX>(ops, tables, P, K, u0, u0_broadcast, uT, tol, stats, flags, s)
-    const bool full = (nx == 64 * sh.PX);
-    if (sh.PX == 1 && sh.NW == 2) { if (full) { MG_FOR_SHAPE(1, 16, 2, true, MG_CALL_EXPMV) } else { MG_FOR_SHAPE(1, 16, 2, false, MG_CALL_EXPMV) } }
-    if (sh.PX == 1 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(1, 16, 4, true, MG_CALL_EXPMV) } else { MG_FOR_SHAPE(1, 16, 4, false, MG_CALL_EXPMV) } }
-    if (sh.PX == 1 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(1, 16, 8, true, MG_CALL_EXPMV) } else { MG_FOR_SHAPE(1, 16, 8, false, MG_CALL_EXPMV) } }
-    if (sh.PX == 2 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(2, 16, 4, true, MG_CALL_EXPMV) } else { MG_FOR_SHAPE(2, 16, 4, false, MG_CALL_EXPMV) } }
-    if (sh.PX == 2 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(2, 16, 8, true, MG_CALL_EXPMV) } else { MG_FOR_SHAPE(2, 16, 8, false, MG_CALL_EXPMV) } }
+#define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX)                                       \
+    run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX>(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, \
+                                              tol, precision, stats, flags, s)
+    MG_DISPATCH(MG_CALL_EXPMV)
 #undef MG_CALL_EXPMV
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const double* dWE,
@@ -526,12 +536,6 @@ hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const 
     const int qmax = ops->qmax;
 #define MG_CALL_EULER(PX, RJ, NW, R0, R1, R2, QM, FX) \
     run_euler<PX, RJ, NW, R0, R1, R2, 1, FX>(ops, u, P, dWE, NE, dt, flags, s)
-    const bool full = (nx == 64 * sh.PX);
-    if (sh.PX == 1 && sh.NW == 2) { if (full) { MG_FOR_SHAPE(1, 16, 2, true, MG_CALL_EULER) } else { MG_FOR_SHAPE(1, 16, 2, false, MG_CALL_EULER) } }
-    if (sh.PX == 1 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(1, 16, 4, true, MG_CALL_EULER) } else { MG_FOR_SHAPE(1, 16, 4, false, MG_CALL_EULER) } }
-    if (sh.PX == 1 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(1, 16, 8, true, MG_CALL_EULER) } else { MG_FOR_SHAPE(1, 16, 8, false, MG_CALL_EULER) } }
-    if (sh.PX == 2 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(2, 16, 4, true, MG_CALL_EULER) } else { MG_FOR_SHAPE(2, 16, 4, false, MG_CALL_EULER) } }
-    if (sh.PX == 2 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(2, 16, 8, true, MG_CALL_EULER) } else { MG_FOR_SHAPE(2, 16, 8, false, MG_CALL_EULER) } }
+    MG_DISPATCH(MG_CALL_EULER)
 #undef MG_CALL_EULER
-    return hipErrorInvalidValue;
 }

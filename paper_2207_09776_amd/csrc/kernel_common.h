@@ -1,0 +1,307 @@
+// Device helpers shared by the Taylor-chain kernels (register-resident and
+// cooperative): DPP lane shifts, wave reductions, the banded-Kronecker row
+// operator, LDS halo slots and the per-(path, step) table view.
+#pragma once
+
+#include <cmath>
+
+#include "mg_internal.h"
+
+namespace mgk {
+
+// ---- per-type lane shifts, max and broadcast ---------------------------------
+// wave_shr:1 (lane l receives lane l-1) and wave_shl:1 (lane l receives l+1),
+// zero fill beyond the wave.
+template <class T> __device__ T from_left(T x);
+template <class T> __device__ T from_right(T x);
+template <> __device__ inline double from_left<double>(double x) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x138, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x138, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <> __device__ inline double from_right<double>(double x) {
+    int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x130, 0xf, 0xf, true);
+    int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x130, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <> __device__ inline float from_left<float>(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, true));
+}
+template <> __device__ inline float from_right<float>(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, true));
+}
+
+// max(acc, |x|) as one v_max with an abs source modifier (fmax() adds an IEEE
+// canonicalisation per operand).  NaN inputs may be dropped; non-finite
+// states are detected separately at the end of the launch.
+__device__ inline double max_abs(double acc, double x) {
+    double r;
+    asm("v_max_f64 %0, %1, |%2|" : "=v"(r) : "v"(acc), "v"(x));
+    return r;
+}
+__device__ inline float max_abs(float acc, float x) {
+    float r;
+    asm("v_max_f32 %0, %1, |%2|" : "=v"(r) : "v"(acc), "v"(x));
+    return r;
+}
+
+template <class T>
+__device__ inline T wave_max(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = max_abs(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Wave-uniform copy of a value every lane holds identically.
+__device__ inline double uniform(double x) {
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float uniform(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Dt y at this lane's PX points: y[q+1] - y[q-1] with neighbours from the
+// adjacent lanes (zero beyond the wave, which is the zero boundary).
+template <int PX, class T>
+__device__ inline void dt_apply(const T (&y)[PX], T (&out)[PX]) {
+    const T left = from_left<T>(y[PX - 1]);
+    const T right = from_right<T>(y[0]);
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        const T a = (q + 1 < PX) ? y[q + 1] : right;
+        const T b = (q > 0) ? y[q - 1] : left;
+        out[q] = a - b;
+    }
+}
+
+template <int R0, int R1, int R2>
+struct Bands {
+    static constexpr int RH = (R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2));
+    static constexpr int O1 = 2 * R0 + 1;
+    static constexpr int O2 = O1 + 2 * R1 + 1;
+    static constexpr int NB = O2 + 2 * R2 + 1;
+    static constexpr int NBP = (NB + 1) & ~1;
+};
+
+// One application of the banded-Kronecker operator to the RJ rows of this
+// wave into a separate output array.  `din(rr, q)` yields the input row rr in
+// [-RH, RJ + RH).  `coef(r, e)` is the coefficient e of local row r; rows
+// beyond nv have zero coefficients in the (padded) tables, so they produce
+// zeros without a branch.  QMAX is the highest power of Dt present.
+template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, class T, class In,
+          class Coef>
+__device__ inline void apply_operator(In din, Coef coef, int lane, int nx, T (&out)[RJ][PX]) {
+    using BD = Bands<R0, R1, R2>;
+    constexpr int NB = BD::NB;
+    T cur[NB], nxt[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) cur[e] = coef(0, e);
+#pragma unroll
+    for (int r = 0; r < RJ; ++r) {
+        if (r + 1 < RJ) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) nxt[e] = coef(r + 1, e);
+        }
+        T y0[PX], y1[PX], y2[PX];
+#pragma unroll
+        for (int q = 0; q < PX; ++q) y0[q] = y1[q] = y2[q] = T(0);
+#pragma unroll
+        for (int b = -R0; b <= R0; ++b)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) y0[q] = fma(cur[b + R0], din(r + b, q), y0[q]);
+        if (QMAX >= 1) {
+#pragma unroll
+            for (int b = -R1; b <= R1; ++b)
+#pragma unroll
+                for (int q = 0; q < PX; ++q)
+                    y1[q] = fma(cur[BD::O1 + b + R1], din(r + b, q), y1[q]);
+        }
+        if (QMAX >= 2) {
+#pragma unroll
+            for (int b = -R2; b <= R2; ++b)
+#pragma unroll
+                for (int q = 0; q < PX; ++q)
+                    y2[q] = fma(cur[BD::O2 + b + R2], din(r + b, q), y2[q]);
+            T t[PX];
+            dt_apply<PX, T>(y2, t);
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                y1[q] += t[q];
+                // the inner Dt result lives on the grid only (truncated product)
+                if (!FULLX && lane * PX + q >= nx) y1[q] = T(0);
+            }
+        }
+        if (QMAX >= 1) {
+            T t[PX];
+            dt_apply<PX, T>(y1, t);
+#pragma unroll
+            for (int q = 0; q < PX; ++q) y0[q] += t[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PX; ++q) out[r][q] = (!FULLX && lane * PX + q >= nx) ? T(0) : y0[q];
+        if (r + 1 < RJ) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) cur[e] = nxt[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// One application of the banded-Kronecker operator to the RJ rows of this
+// wave, in place: d holds the input rows, top/bot the RH halo rows above and
+// below.  Row r of the result y is handed to `emit(r, y)`, which returns the
+// value that replaces d[r]; the replacement is committed RH rows later, once
+// no later row reads the old d[r], so only RH + 1 result rows are live at a
+// time.  `coef(r, e)` is the coefficient e of local row r; rows beyond nv have
+// zero coefficients in the (padded) tables, so they produce zeros without a
+// branch.  QMAX is the highest power of Dt present.
+template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, class T,
+          class Coef, class Emit>
+__device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
+                                     const T (&bot)[RH][PX], Coef coef, int lane, int nx,
+                                     Emit emit) {
+    using BD = Bands<R0, R1, R2>;
+    constexpr int NB = BD::NB;
+    auto din = [&](int rr, int q) -> T {
+        if (rr < 0) return top[rr + RH][q];
+        if (rr >= RJ) return bot[rr - RJ][q];
+        return d[rr][q];
+    };
+    T res[RJ][PX];
+    // coefficients of the current row; the next row's are loaded while the
+    // current one is computed (scheduling barriers keep the scalar loads from
+    // being hoisted all at once)
+    T cur[NB], nxt[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) cur[e] = coef(0, e);
+#pragma unroll
+    for (int r = 0; r < RJ; ++r) {
+        if (r + 1 < RJ) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) nxt[e] = coef(r + 1, e);
+        }
+        T y0[PX], y1[PX], y2[PX];
+#pragma unroll
+        for (int q = 0; q < PX; ++q) y0[q] = y1[q] = y2[q] = T(0);
+#pragma unroll
+        for (int b = -R0; b <= R0; ++b)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) y0[q] = fma(cur[b + R0], din(r + b, q), y0[q]);
+        if (QMAX >= 1) {
+#pragma unroll
+            for (int b = -R1; b <= R1; ++b)
+#pragma unroll
+                for (int q = 0; q < PX; ++q)
+                    y1[q] = fma(cur[BD::O1 + b + R1], din(r + b, q), y1[q]);
+        }
+        if (QMAX >= 2) {
+#pragma unroll
+            for (int b = -R2; b <= R2; ++b)
+#pragma unroll
+                for (int q = 0; q < PX; ++q)
+                    y2[q] = fma(cur[BD::O2 + b + R2], din(r + b, q), y2[q]);
+            T t[PX];
+            dt_apply<PX, T>(y2, t);
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                y1[q] += t[q];
+                // the inner Dt result lives on the grid only (truncated product)
+                if (!FULLX && lane * PX + q >= nx) y1[q] = T(0);
+            }
+        }
+        if (QMAX >= 1) {
+            T t[PX];
+            dt_apply<PX, T>(y1, t);
+#pragma unroll
+            for (int q = 0; q < PX; ++q) y0[q] += t[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PX; ++q)
+            if (!FULLX && lane * PX + q >= nx) y0[q] = T(0);
+        emit(r, y0);
+#pragma unroll
+        for (int q = 0; q < PX; ++q) res[r][q] = y0[q];
+        if (r >= RH) {
+#pragma unroll
+            for (int q = 0; q < PX; ++q) d[r - RH][q] = res[r - RH][q];
+        }
+        if (r + 1 < RJ) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) cur[e] = nxt[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = (RJ > RH ? RJ - RH : 0); r < RJ; ++r)
+#pragma unroll
+        for (int q = 0; q < PX; ++q) d[r][q] = res[r][q];
+}
+
+// LDS halo layout: halo[parity][wave + 1][slot][64*PX] for waves -1 .. NW; the
+// guard waves -1 and NW are zero rows (the zero boundary in v) so that every
+// fetch is unconditional.  Slots 0..RH-1 hold a wave's first RH rows, slots
+// RH..2RH-1 its last RH rows.
+template <int PX, int RJ, int NW, int RH, class T>
+struct Halo {
+    T* base;
+    __device__ T* slot(int par, int w, int s) const {
+        return base + (((size_t)par * (NW + 2) + (w + 1)) * (2 * RH) + s) * (64 * PX);
+    }
+    __device__ void zero_guards(int tid, int nthreads) const {
+        for (int par = 0; par < 2; ++par)
+            for (int g = 0; g < 2; ++g) {
+                T* p = slot(par, g == 0 ? -1 : NW, 0);
+                for (int i = tid; i < 2 * RH * 64 * PX; i += nthreads) p[i] = T(0);
+            }
+    }
+    __device__ void publish(int par, int w, int lane, const T (&d)[RJ][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s) {
+            T* top = slot(par, w, s) + lane * PX;
+            T* bot = slot(par, w, RH + s) + lane * PX;
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                top[q] = d[s][q];
+                bot[q] = d[RJ - RH + s][q];
+            }
+        }
+    }
+    // rows -RH..-1 (from wave w-1) and RJ..RJ+RH-1 (from wave w+1)
+    __device__ void fetch(int par, int w, int lane, T (&top)[RH][PX], T (&bot)[RH][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s) {
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                top[s][q] = slot(par, w - 1, RH + s)[lane * PX + q];
+                bot[s][q] = slot(par, w + 1, s)[lane * PX + q];
+            }
+        }
+    }
+};
+
+template <int PX, int NW, int RH, class T>
+constexpr size_t halo_bytes() {
+    return (size_t)2 * (NW + 2) * 2 * RH * 64 * PX * sizeof(T);
+}
+
+// LDS: halo | red [2][NW][2] (term norms) | red2 [2][NW] (state norms) | flag
+template <int PX, int NW, int RH, class T>
+constexpr size_t resident_lds_bytes() {
+    return halo_bytes<PX, NW, RH, T>() + (size_t)2 * NW * 2 * sizeof(T) +
+           (size_t)2 * NW * sizeof(T) + 16;
+}
+
+// Table of one (path, step): 64-byte header, then rows of NBP coefficients.
+struct TableView {
+    const char* base;
+    __device__ int s() const { return reinterpret_cast<const int32_t*>(base)[0]; }
+    __device__ int m() const { return reinterpret_cast<const int32_t*>(base)[2]; }
+    __device__ double es() const { return reinterpret_cast<const double*>(base)[2]; }
+    __device__ int flag() const { return reinterpret_cast<const int32_t*>(base)[10]; }
+    template <class T>
+    __device__ const T* rows() const { return reinterpret_cast<const T*>(base + 64); }
+};
+
+
+}  // namespace mgk

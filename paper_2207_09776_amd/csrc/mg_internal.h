@@ -37,12 +37,15 @@ struct mg_ops {
 };
 
 // Per-(path, step) table of the scaled Magnus logarithm (written by the
-// assemble kernel, read by the Taylor kernels).  Layout per (p,k), FP64:
-//   [0] s (int32)  [1] m (int32)  [2] exp(mu/s)  [3] mu  [4] ||Y - mu I||_1
-//   [5] flag (int32)  then nv rows of NBP coefficients of (Y - mu I)/s.
-inline size_t mg_table_stride(const mg_ops* ops) {
-    size_t s = (size_t)MG_HDR + (size_t)ops->nv_pad * ops->NBP;
-    return (s + 7) & ~(size_t)7;   // 64-byte aligned records
+// assemble kernel, read by the Taylor kernels).  Layout per (p,k):
+//   64-byte header: [int32 s, pad] [int32 m, pad] [f64 exp(mu/s)] [f64 mu]
+//                   [f64 ||Y - mu I||_1] [int32 flag, pad] [2 x f64 reserved]
+//   then nv_pad rows of NBP coefficients of (Y - mu I)/s, FP64 (MG_FP64) or
+//   FP32 rounded once from FP64 (MG_FP32C); records are 64-byte aligned.
+inline size_t mg_table_bytes(const mg_ops* ops, int precision) {
+    const size_t elem = precision == MG_FP32C ? 4 : 8;
+    size_t b = 64 + (size_t)ops->nv_pad * ops->NBP * elem;
+    return (b + 63) & ~(size_t)63;
 }
 
 // error state (thread local, defined in api.hip)
@@ -54,12 +57,13 @@ hipError_t launch_iterated_integrals(const double* dW, int64_t P, int64_t Nf, do
 hipError_t launch_euler_increments(const double* dW, int64_t P, int64_t Nf, int NE, double* dWE,
                                    hipStream_t s);
 hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int K, double tol,
-                           int precision, double* tables, hipStream_t s);
+                           int precision, char* tables, hipStream_t s);
 // Taylor chain over all K steps for paths whose state fits on one workgroup.
 // Returns hipErrorInvalidValue (without launching) if no kernel shape fits.
-hipError_t launch_expmv_resident(const mg_ops* ops, const double* tables, int64_t P, int K,
-                                 const double* u0, int u0_broadcast, double* uT, double tol,
-                                 int32_t* stats, int32_t* flags, hipStream_t s, bool dry_run);
+hipError_t launch_expmv_resident(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
+                                 int K, const double* u0, int u0_broadcast, double* uT, double tol,
+                                 int precision, int32_t* stats, int32_t* flags, hipStream_t s,
+                                 bool dry_run);
 hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const double* dWE,
                                  int NE, double dt, int32_t* flags, hipStream_t s, bool dry_run);
 hipError_t launch_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const double* pathstat,
@@ -68,6 +72,21 @@ hipError_t launch_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const 
 
 // rows covered by the resident kernel shape for this grid (0: no shape)
 int resident_rows(int nx, int nv);
+// rows per workgroup of the cooperative kernel for this nx (0: no shape)
+int coop_rows_per_group_member(int nx);
+
+// Cooperative launch plan: G workgroups per path, ngroups resident groups and
+// the exchange area they need (placed after the tables in the workspace).
+struct CoopPlan {
+    int G = 0, ngroups = 0, xcd_map = 0, threads = 0, per_cu = -1, cus = -1;
+    int stage = 0;   // how far planning got (diagnostics)
+    size_t lds = 0, xh_bytes = 0, xn_bytes = 0, fl_bytes = 0, bytes = 0;
+};
+hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan);
+hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
+                             int K, const double* u0, int u0_broadcast, double* uT, double tol,
+                             int precision, int32_t* stats, int32_t* flags, char* xarea,
+                             const CoopPlan& plan, hipStream_t s);
 
 // host operator build (ops_build.cpp)
 mg_status mg_build_host(const mg_grid* grid, const mg_coeffs* coeffs, int order, mg_ops* ops);

@@ -170,22 +170,29 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     if (!ok) return mg_fail(MG_EUNSUPPORTED, "x-derivative power above 2 in the Magnus basis");
 
     const int nact = order == 1 ? 2 : (order == 2 ? 4 : 6);
-    // Band radii actually used, after dropping cancellation residues (entries
-    // below 1e-14 of the largest entry of the same factor are exact zeros in
-    // exact arithmetic; they stem from rounding in the products).
+    // Band radii actually used, after dropping cancellation residues.  A
+    // factor V_q multiplies (D^x)^q, whose norm is about (1/dx)^q, so entries
+    // are compared with the whole matrix through the weight (1/dx)^q: entries
+    // below 1e-14 of the largest weighted entry of the same basis matrix are
+    // zero in exact arithmetic and stem from rounding in the products (a
+    // factor can consist of residues only, e.g. the D^x part of [[B,A],B] for
+    // the constant-coefficient operator).
     int R[3] = {0, 0, 0};
-    for (int l = 0; l < MG_NBASIS; ++l)
+    const double wq[3] = {1.0, 1.0 / dx, 1.0 / (dx * dx)};
+    for (int l = 0; l < MG_NBASIS; ++l) {
+        double mx = 0.0;
+        for (int q = 0; q < 3; ++q)
+            for (double v : M[l].V[q].a) mx = std::max(mx, std::fabs(v) * wq[q]);
         for (int q = 0; q < 3; ++q) {
             Band& V = M[l].V[q];
-            double mx = 0.0;
-            for (double v : V.a) mx = std::max(mx, std::fabs(v));
             for (double& v : V.a)
-                if (std::fabs(v) <= 1e-14 * mx) v = 0.0;
+                if (std::fabs(v) * wq[q] <= 1e-14 * mx) v = 0.0;
             if (l >= nact) continue;
             for (int i = 0; i < nv; ++i)
                 for (int o = -V.r; o <= V.r; ++o)
                     if (V.get(i, i + o) != 0.0) R[q] = std::max(R[q], std::abs(o));
         }
+    }
     // highest power of D^x with a non-zero factor among the active matrices
     int qmax = 0;
     for (int l = 0; l < nact; ++l)
@@ -210,7 +217,13 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     for (int q = 0; q < 3; ++q) ops->R[q] = R[q];
     ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (2 * R[2] + 1);
     ops->NBP = (ops->NB + 1) & ~1;
-    ops->nv_pad = std::max(nv, resident_rows(nx, nv));
+    // table rows are padded to the rows the kernel shape covers
+    int rows = resident_rows(nx, nv);
+    if (rows == 0) {
+        const int rw = coop_rows_per_group_member(nx);
+        if (rw > 0) rows = (nv + rw - 1) / rw * rw;
+    }
+    ops->nv_pad = std::max(nv, rows);
     ops->basis_host.assign((size_t)MG_NBASIS * ops->nv_pad * ops->NBP, 0.0);
     const double fold[3] = {1.0, 1.0 / (2.0 * dx), 1.0 / (4.0 * dx * dx)};
     for (int l = 0; l < MG_NBASIS; ++l)

@@ -225,3 +225,81 @@ def test_error_vs_exact_matches_oracle(kappa):
         assert abs(err[p].item() - errors.relative_error(uex.reshape(n, n), u[p].reshape(n, n), kappa)) <= 1e-12
         want2 = errors.relative_error(u[P - 1 - p].reshape(n, n), u[p].reshape(n, n), kappa)
         assert abs(err2[p].item() - want2) <= 1e-12 * max(want2, 1e-3)
+
+
+# ------------------------------------------------------------------ FP32C
+F32_CASES = [
+    ("f32c-24x24-m2", 24, 24, -5.0, 5.0, 2, 3, 4, 256),
+    ("f32c-64x64-m3", 64, 64, -5.0, 5.0, 3, 2, 8, 512),
+    ("f32c-100x90-m2", 100, 90, -6.0, 6.0, 2, 2, 8, 512),
+    ("f32c-128x128-m2", 128, 128, -6.0, 6.0, 2, 2, 16, 2 ** 14),
+]
+
+
+@pytest.mark.parametrize("case", F32_CASES, ids=[c[0] for c in F32_CASES])
+def test_fp32c_matches_oracle(case):
+    """Compensated FP32 form: within 1e-5 relative of the FP64 oracle."""
+    name, nx, nv, lo, hi, order, P, K, Nf = case
+    say(f"magnus {name}")
+    coeffs = wl.langevin_constant(1.0, 0.5)
+    g, B, A, basis, ops = setup_problem(nx, nv, lo, hi, coeffs, order)
+    dW = wl.brownian_increments(17, P, Nf)
+    u0 = wl.gaussian_density(nx, nv, lo, hi, lo, hi, 0.25).reshape(-1)
+    coef, _ = mg.iterated_integrals(to_dev(dW), 1.0, K, order)
+    uT, flags, stats = mg.magnus_expmv(ops, coef, to_dev(u0), precision="fp32c", want_stats=True)
+    u64, _, st64 = mg.magnus_expmv(ops, coef, to_dev(u0), want_stats=True)
+    torch.cuda.synchronize()
+    want = magnus.iterated_magnus_paths(basis, integrals.path_coefficients(dW, 1.0, K, order), u0)
+    for p in range(P):
+        assert rel(uT[p].cpu().numpy(), want[p]) <= 1e-5, (name, p, rel(uT[p].cpu().numpy(), want[p]))
+    assert int(flags.abs().sum()) == 0
+    # the 2^-24 tolerance needs no more Taylor terms than 2^-53
+    assert int(stats[..., 0].sum()) <= int(st64[..., 0].sum())
+
+
+# ------------------------------------------------------------------ cooperative (nx > 128)
+COOP_CASES = [
+    # (name, nx, nv, lo, hi, order, P, K, Nf, T, precision, tol)
+    ("coop-256x256-m2-f64", 256, 256, -5.0, 5.0, 2, 3, 2, 256, 0.25, "fp64", 1e-10),
+    ("coop-256x256-m3-f64", 256, 256, -5.0, 5.0, 3, 2, 2, 256, 0.25, "fp64", 1e-10),
+    ("coop-200x150-m2-f64", 200, 150, -5.0, 5.0, 2, 2, 2, 256, 0.25, "fp64", 1e-10),
+    ("coop-256x256-m2-f32c", 256, 256, -5.0, 5.0, 2, 3, 2, 256, 0.25, "fp32c", 1e-5),
+    ("coop-512x512-m2-f32c", 512, 512, -5.0, 5.0, 2, 1, 1, 64, 0.05, "fp32c", 1e-5),
+]
+
+
+@pytest.mark.parametrize("case", COOP_CASES, ids=[c[0] for c in COOP_CASES])
+def test_coop_matches_oracle(case):
+    name, nx, nv, lo, hi, order, P, K, Nf, T, prec, tol = case
+    say(f"magnus {name}")
+    coeffs = wl.langevin_constant(1.0, 0.5)
+    g, B, A, basis, ops = setup_problem(nx, nv, lo, hi, coeffs, order)
+    dW = wl.brownian_increments(23, P, Nf, T=T)
+    u0 = wl.gaussian_density(nx, nv, lo, hi, lo, hi, 0.25).reshape(-1)
+    coef, _ = mg.iterated_integrals(to_dev(dW), T, K, order)
+    uT, flags, stats = mg.magnus_expmv(ops, coef, to_dev(u0), precision=prec, want_stats=True)
+    torch.cuda.synchronize()
+    assert int(flags.abs().sum()) == 0, flags.cpu().numpy()
+    want = magnus.iterated_magnus_paths(basis, integrals.path_coefficients(dW, T, K, order), u0)
+    for p in range(P):
+        e = rel(uT[p].cpu().numpy(), want[p])
+        assert e <= tol, (name, p, e)
+
+
+def test_full_size_256_fp32c_sampled_path():
+    """The 256x256 workload (4096 paths, m3, 32 steps, compensated FP32) in
+    the configuration the benchmark would run; path 1234 is checked against
+    the FP64 oracle (1e-5)."""
+    w = wl.WORKLOADS["const-256-p4096-m3-k32-fp32c"]
+    say(f"magnus full {w.name}")
+    g, B, A, basis, ops = setup_problem(w.n, w.n, w.lo, w.hi, w.coefficients(), w.order)
+    dW = wl.brownian_increments(w.seed, w.paths, w.Nf)
+    u0 = wl.gaussian_density(w.n, w.n, w.lo, w.hi, w.lo, w.hi, w.s0sq).reshape(-1)
+    coef, _ = mg.iterated_integrals(to_dev(dW), w.T, w.K, w.order)
+    uT, flags, _ = mg.magnus_expmv(ops, coef, to_dev(u0), precision="fp32c")
+    torch.cuda.synchronize()
+    assert int(flags.abs().sum()) == 0
+    p = 1234
+    c = integrals.path_coefficients(dW[p:p + 1], w.T, w.K, w.order)[0]
+    want = magnus.iterated_magnus(basis, c, u0)
+    assert rel(uT[p].cpu().numpy(), want) <= 1e-5
