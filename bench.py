@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--workload", default="const-128-p1024-m2-k16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-euler", action="store_true", help="skip the Euler baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (torch copy_ kernel) so "
+                         "that profiler byte counters can be scaled against a known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: each path is independent "
@@ -135,6 +138,16 @@ def main():
         _, flags, st = mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws, want_stats=with_stats)
         mg.error_vs_exact(ops, uT, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T, err=err)
         return flags, st
+
+    if args.copy_calibration:
+        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev)     # 1 GiB
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1073741824 bytes read and written by one copy kernel")
+        del src, dst
 
     # warm-up (also gives the Taylor statistics and the flags)
     flags, st = step(with_stats=True)
