@@ -41,6 +41,27 @@ NNZ_ROW = {1: 5, 2: 11, 3: 15}
 EULER_FLOPS_PT = 2 * 5 + 1            # u + (dt B + dW A) u: 5 non-zeros per row, + update
 
 
+# HBM bytes per launch of the Taylor kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch), scaled by the factors the same counters give
+# for a plain 1 GiB copy kernel (fetch x 2.000, write x 1.000).  Valid only for
+# the kernel source they were measured on: the key is a hash of that source.
+TRAFFIC = {}
+
+
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("expmv_resident.hip", "kernel_common.h"):
+        with open(os.path.join(ROOT, "paper_2207_09776_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(workload):
+    rec = TRAFFIC.get((_kernel_source_hash(), workload))
+    return None if rec is None else rec[0] + rec[1]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -101,6 +122,7 @@ def main():
     ap.add_argument("--workload", default="const-128-p1024-m2-k16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-euler", action="store_true", help="skip the Euler baseline")
+    ap.add_argument("--no-fp32c", action="store_true", help="skip the compensated FP32 run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (torch copy_ kernel) so "
                          "that profiler byte counters can be scaled against a known size")
@@ -133,9 +155,10 @@ def main():
     ws = torch.empty(mg.workspace_bytes(ops, P, K), dtype=torch.uint8, device=dev)
     stats = torch.zeros((P, K, 2), dtype=torch.int32, device=dev)
 
-    def step(with_stats=False):
+    def step(precision, with_stats=False):
         mg.iterated_integrals(dW, w.T, K, w.order, coef=coef, pathstat=ps)
-        _, flags, st = mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws, want_stats=with_stats)
+        _, flags, st = mg.magnus_expmv(ops, coef, u0, precision=precision, uT=uT, ws=ws,
+                                       want_stats=with_stats)
         mg.error_vs_exact(ops, uT, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T, err=err)
         return flags, st
 
@@ -149,46 +172,53 @@ def main():
         log("copy calibration: 1073741824 bytes read and written by one copy kernel")
         del src, dst
 
-    # warm-up (also gives the Taylor statistics and the flags)
-    flags, st = step(with_stats=True)
-    for _ in range(max(0, args.warmup - 1)):
-        step()
-    torch.cuda.synchronize()
-    stats_np = st.cpu().numpy()
-    nflag = int((flags != 0).sum())
-    mean_err = float(err.mean())
-    log(f"warm-up done: mean Err {mean_err:.4e}, flagged paths {nflag}")
+    def measure(precision, steps, warmup):
+        """Warm-up (with Taylor statistics), then `steps` timed passes."""
+        flags, st = step(precision, with_stats=True)
+        for _ in range(max(0, warmup - 1)):
+            step(precision)
+        torch.cuda.synchronize()
+        res = {"stats": st.cpu().numpy(), "flagged": int((flags != 0).sum()),
+               "mean_err": float(err.mean()), "err_head": float(err[:64].mean())}
+        mg.timing_reset()
+        mg.timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            step(precision)
+        ev1.record()
+        torch.cuda.synchronize()
+        res["wall_ms"] = (time.perf_counter() - t0) * 1e3 / steps
+        mg.timing_enable(False)
+        res["ms_per_step"] = ev0.elapsed_time(ev1) / steps
+        k_ms, k_n = mg.timing_read("expmv")
+        res["launch_ms"] = k_ms / max(k_n, 1)
+        res["terms"] = int(res["stats"][..., 0].sum())
+        res["substeps"] = int(res["stats"][..., 1].sum())
+        return res
 
-    mg.timing_reset()
-    mg.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    mg.timing_enable(False)
-    gpu_ms = ev0.elapsed_time(ev1)
-    k_ms, k_n = mg.timing_read("expmv")
-    ms_per_step = gpu_ms / args.steps
+    m64 = measure("fp64", args.steps, args.warmup)
+    ms_per_step = m64["ms_per_step"]
     paths_per_s = P / (ms_per_step / 1e3)
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f}), "
-        f"Taylor kernel {k_ms / max(k_n, 1):.3f} ms/launch over {k_n} launches")
+    mean_err = m64["mean_err"]
+    nflag = m64["flagged"]
+    log(f"FP64: mean Err {mean_err:.4e}, flagged paths {nflag}; {ms_per_step:.3f} ms/step "
+        f"(wall {m64['wall_ms']:.3f}), Taylor kernel {m64['launch_ms']:.3f} ms/launch")
 
     # algorithmic work of the dominant kernel (per launch)
-    terms = int(stats_np[..., 0].sum())
+    terms = m64["terms"]
     flops_pt = 2 * NNZ_ROW[w.order] + 2
     flops = float(terms) * N * flops_pt
-    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    k_avg_s = m64["launch_ms"] / 1e3
     achieved = flops / k_avg_s
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
+                "traffic": traffic_for(w.name),
                 "kernel": "expmv_resident_kernel",
                 "flops_per_point_term": flops_pt, "taylor_terms": terms,
-                "terms_per_path": terms / P, "substeps_per_path": float(stats_np[..., 1].sum()) / P,
+                "terms_per_path": terms / P, "substeps_per_path": m64["substeps"] / P,
                 "launch_ms": k_avg_s * 1e3}
     # bytes a streaming (HBM-resident) Taylor chain would have to move: read the
     # term and the partial sum, write both, 8 B each, per point per term
@@ -196,14 +226,29 @@ def main():
     extra = {"streaming_equivalent_GBps": streaming_bytes / k_avg_s / 1e9,
              "hbm_bytes_min_per_launch": float(P * N * 8 + N * 8 + mg.workspace_bytes(ops, P, K))}
 
+    # compensated FP32 at the same K: errors must agree within 1 % of the FP64 error
+    fp32c = None
+    if not args.no_fp32c:
+        m32 = measure("fp32c", max(1, args.steps // 2), 1)
+        rel = abs(m32["mean_err"] - mean_err) / mean_err
+        fl32 = float(m32["terms"]) * N * flops_pt
+        fp32c = {"paths_per_s": P / (m32["ms_per_step"] / 1e3), "ms_per_step": m32["ms_per_step"],
+                 "launch_ms": m32["launch_ms"], "mean_err": m32["mean_err"],
+                 "err_rel_diff_vs_fp64": rel, "matched": bool(rel <= 0.01),
+                 "flagged_paths": m32["flagged"], "terms_per_path": m32["terms"] / P,
+                 "substeps_per_path": m32["substeps"] / P,
+                 "achieved_TFLOPs": fl32 / (m32["launch_ms"] / 1e3) / 1e12,
+                 "speedup_vs_fp64": ms_per_step / m32["ms_per_step"]}
+        log(f"FP32C: {fp32c['paths_per_s']:.1f} paths/s, Err {m32['mean_err']:.4e} "
+            f"(rel. diff {rel:.2e}), {fp32c['terms_per_path']:.0f} terms/path")
+
     # Euler-Maruyama at matched error
     euler = None
     if not args.no_euler:
         sub = min(64, P)
-        target = 1.02 * float(err[:sub].mean())
-        dWE_full = None
+        target = 1.02 * m64["err_head"]
         chosen = None
-        best = None
+        curve = []
         for q in range(10, int(math.log2(w.Nf)) + 1):
             NE = 2 ** q
             dWE = mg.euler_increments(dW[:sub].contiguous(), NE)
@@ -214,11 +259,13 @@ def main():
             torch.cuda.synchronize()
             me = float(e.mean()) if int((fl != 0).sum()) == 0 else float("inf")
             log(f"euler NE=2^{q}: mean Err {me:.4e} (target {target:.4e})")
-            best = (NE, me) if best is None or me < best[1] else best
+            if math.isfinite(me):
+                curve.append((NE, me))
             if me <= target:
                 chosen = NE
                 break
-        NE = chosen if chosen is not None else best[0]
+        NE = chosen if chosen is not None else (max(curve, key=lambda c: -c[1])[0] if curve
+                                                else 2 ** int(math.log2(w.Nf)))
         dWE_full = mg.euler_increments(dW, NE)
         u = u0.repeat(P, 1).contiguous()
         mg.euler_step(ops, u, dWE_full, w.T / NE)          # warm-up
@@ -236,9 +283,26 @@ def main():
         torch.cuda.synchronize()
         eu_ms = e0.elapsed_time(e1) / reps
         euler = {"steps": NE, "matched": chosen is not None, "mean_err": float(err.mean()),
+                 "target_err_64_paths": target, "curve_64_paths": curve,
                  "paths_per_s": P / (eu_ms / 1e3), "ms_per_batch": eu_ms,
                  "magnus_speedup": (P / (ms_per_step / 1e3)) / (P / (eu_ms / 1e3)),
                  "achieved_TFLOPs": P * NE * N * EULER_FLOPS_PT / (eu_ms / 1e3) / 1e12}
+        if chosen is None and len(curve) >= 2:
+            # no power of two up to the fine resolution reaches the target:
+            # extrapolate Err(N) = a + b N^(-1/2) (strong order 1/2) through the
+            # last two points; the step count and time are labelled as such
+            (n1, e1_), (n2, e2_) = curve[-2], curve[-1]
+            b = (e1_ - e2_) / (n1 ** -0.5 - n2 ** -0.5)
+            a = e2_ - b * n2 ** -0.5
+            ext = {"model": "Err(N) = a + b N^-1/2 through the last two points",
+                   "a": a, "b": b}
+            if target > a and b > 0:
+                nstar = (b / (target - a)) ** 2
+                t_star = eu_ms * nstar / NE
+                ext.update({"steps": nstar, "ms_per_batch": t_star,
+                            "paths_per_s": P / (t_star / 1e3),
+                            "magnus_speedup": t_star / ms_per_step})
+            euler["extrapolated"] = ext
         log(f"euler at NE={NE}: {euler['paths_per_s']:.1f} paths/s, Err {euler['mean_err']:.4e}")
 
     cpu = None
@@ -270,7 +334,7 @@ def main():
         "roofline": roofline,
         "hbm": extra,
         "euler": euler,
-        "fp32c": None,
+        "fp32c": fp32c,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

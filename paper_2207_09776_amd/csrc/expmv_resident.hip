@@ -39,6 +39,50 @@ namespace {
 
 using namespace mgk;
 
+// Early termination without a norm of F at every term.  The test after term j
+// needs ||F_j||, but it can only pass if ||c_{j-1}|| <= tol ||F_j||, and
+// ||F_j|| <= ||F_{j-1}|| + ||c_j|| with ||c_j|| <= tol ||F_j|| give
+// ||F_j|| <= ||F_{j-1}|| / (1 - tol).  With fnest an upper bound of ||F_{j-1}||
+// (the exact norm when it was formed, else the previous bound plus ||c_{j-1}||),
+// ||F_j|| is therefore formed only when ||c_{j-1}|| <= tol fnest / (1 - tol)
+// (times a margin for rounding).  Whenever the test could pass it is evaluated
+// on the exact norms, so the term counts are those of the plain rule.
+template <class T>
+struct StopRule {
+    T tol, kpred;
+    T cprev, fnest;
+    bool wantf;
+    __device__ StopRule(T tol_, T margin) : tol(tol_), kpred(tol_ / (T(1) - tol_) * margin) {}
+    __device__ void start(T unorm) {
+        cprev = unorm;
+        fnest = unorm;
+        wantf = cprev <= kpred * fnest;
+    }
+    // norms of the latest term (c) and, when it was formed, of the partial sum
+    // (fn); true when the series stops before the next term
+    template <class ReadF>
+    __device__ bool stop(T c, ReadF read_fn) {
+        if (wantf) {
+            const T fn = read_fn();
+            if (cprev + c <= tol * fn) return true;
+            fnest = fn;
+        } else {
+            fnest = fnest + c;
+        }
+        cprev = c;
+        wantf = cprev <= kpred * fnest;
+        return false;
+    }
+};
+
+template <class T, int NW>
+__device__ inline T lds_max(const T* v, int stride) {
+    T g = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) g = max_abs(g, v[i * stride]);
+    return uniform(g);
+}
+
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
@@ -51,8 +95,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
-    T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);   // [2][NW][2]
-    T* red2 = red + 2 * NW * 2;                                 // [2][NW]
+    T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);   // [2][NW][2] term norms
+    T* red2 = red + 2 * NW * 2;                                 // [2][NW] state norms
     int* sflag = reinterpret_cast<int*>(red2 + 2 * NW);
 
     const int lane = threadIdx.x & 63;
@@ -75,26 +119,22 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                 F[r][q] = (r < nrows && i < nx) ? src[(size_t)(row0 + r) * nx + i] : 0.0;
             }
     }
-    // ||u||_inf of the state (per-wave partial, LDS, barrier)
-    auto state_norm = [&](int par2) -> T {
-        T m = 0;
+    // per-wave ||u||_inf into red2[par2]; read after the next barrier
+    auto post_state_norm = [&](int par2) {
+        T mx = 0;
 #pragma unroll
         for (int r = 0; r < RJ; ++r)
 #pragma unroll
-            for (int q = 0; q < PX; ++q) m = max_abs(m, F[r][q]);
-        m = wave_max(m);
-        if (lane == 0) red2[par2 * NW + w] = m;
-        __syncthreads();
-        T g = 0;
-        for (int i = 0; i < NW; ++i) g = max_abs(g, red2[par2 * NW + i]);
-        return uniform(g);
+            for (int q = 0; q < PX; ++q) mx = max_abs(mx, F[r][q]);
+        mx = wave_max_dpp(mx);
+        if (lane == 0) red2[par2 * NW + w] = mx;
     };
 
     int sub_par = 0;
-    T unorm = state_norm(sub_par);
-    sub_par ^= 1;
+    post_state_norm(sub_par);
     int tpar = 0;
     int pflag = 0;
+    StopRule<T> rule(tol, 1.0 + 0x1p-30);
 
     for (int k = 0; k < K; ++k) {
         const TableView tv{tables + ((size_t)p * K + k) * tbytes};
@@ -103,67 +143,69 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
         const double es = tv.es();
         pflag |= tv.flag();
         const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
-        auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
         int terms = 0;
         for (int sub = 0; sub < s; ++sub) {
-            T d[RJ][PX];
+            // the Taylor terms alternate between A and B (no copies between terms)
+            T A[RJ][PX], B[RJ][PX];
 #pragma unroll
             for (int r = 0; r < RJ; ++r)
 #pragma unroll
-                for (int q = 0; q < PX; ++q) d[r][q] = F[r][q];
-            T c1 = unorm;
+                for (int q = 0; q < PX; ++q) A[r][q] = F[r][q];
+            // a sub-step without terms still orders the state-norm slots
+            if (m == 0) __syncthreads();
             T fj = 1;
-            for (int j = 1; j <= m; ++j) {
-                halo.publish(tpar, w, lane, d);
+            // term j from `in` into `out`; false when the series stopped before it
+            auto step = [&](T (&in)[RJ][PX], T (&out)[RJ][PX], int j) -> bool {
+                halo.publish(tpar, w, lane, in);
                 __syncthreads();
-                if (j > 1) {
-                    // norms of term j-1, published before this barrier
-                    T c2 = 0, fn = 0;
+                if (j == 1) {
+                    rule.start(lds_max<T, NW>(red2 + sub_par * NW, 1));
+                } else {
                     const T* rr = red + (size_t)(tpar ^ 1) * NW * 2;
-                    for (int i = 0; i < NW; ++i) {
-                        c2 = max_abs(c2, rr[2 * i]);
-                        fn = max_abs(fn, rr[2 * i + 1]);
-                    }
-                    c2 = uniform(c2);
-                    fn = uniform(fn);
-                    if (c1 + c2 <= tol * fn) break;
-                    c1 = c2;
+                    if (rule.stop(lds_max<T, NW>(rr, 2), [&] { return lds_max<T, NW>(rr + 1, 2); }))
+                        return false;
                 }
                 T top[RH][PX], bot[RH][PX];
-                halo.fetch(tpar, w, lane, top, bot);
-                auto din = [&](int rr, int q) -> T {
-                    if (rr < 0) return top[rr + RH][q];
-                    if (rr >= RJ) return bot[rr - RJ][q];
-                    return d[rr][q];
-                };
-                T dn[RJ][PX];
-                apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX, T>(din, coef, lane, nx, dn);
+                const int hp = tpar;
+                auto fb = [&] { halo.fetch_bot(hp, w, lane, bot); };
+                auto ft = [&] { halo.fetch_top(hp, w, lane, top); };
+                auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
                 fj /= (T)j;             // 1/j!
                 T mc = 0, mf = 0;
+                apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(
+                    in, out, top, bot, fb, ft, coef, lane, nx, [&](int r, T (&y)[PX]) {
 #pragma unroll
-                for (int r = 0; r < RJ; ++r)
+                        for (int q = 0; q < PX; ++q) {
+                            F[r][q] = fma(y[q], fj, F[r][q]);
+                            mc = max_abs(mc, y[q]);
+                        }
+                    });
+                if (rule.wantf) {
 #pragma unroll
-                    for (int q = 0; q < PX; ++q) {
-                        d[r][q] = dn[r][q];
-                        F[r][q] = fma(dn[r][q], fj, F[r][q]);
-                        mc = max_abs(mc, dn[r][q]);
-                        mf = max_abs(mf, F[r][q]);
-                    }
-                mc = wave_max(mc) * fj;
-                mf = wave_max(mf);
+                    for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                        for (int q = 0; q < PX; ++q) mf = max_abs(mf, F[r][q]);
+                    mf = wave_max_dpp(mf);
+                }
+                mc = wave_max_dpp(mc) * fj;
                 if (lane == 0) {
                     red[(size_t)tpar * NW * 2 + 2 * w] = mc;
                     red[(size_t)tpar * NW * 2 + 2 * w + 1] = mf;
                 }
                 tpar ^= 1;
                 ++terms;
+                return true;
+            };
+            for (int j = 1; j <= m; j += 2) {
+                if (!step(A, B, j)) break;
+                if (j + 1 > m || !step(B, A, j + 1)) break;
             }
 #pragma unroll
             for (int r = 0; r < RJ; ++r)
 #pragma unroll
                 for (int q = 0; q < PX; ++q) F[r][q] *= es;
-            unorm = state_norm(sub_par);
             sub_par ^= 1;
+            post_state_norm(sub_par);
         }
         if (stats && threadIdx.x == 0) {
             stats[((size_t)p * K + k) * 2] = terms;
@@ -228,25 +270,21 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                 lo[r][q] = (float)(u - (double)hi[r][q]);
             }
     }
-    auto state_norm = [&](int par2) -> T {
-        T m = 0;
+    auto post_state_norm = [&](int par2) {
+        T mx = 0;
 #pragma unroll
         for (int r = 0; r < RJ; ++r)
 #pragma unroll
-            for (int q = 0; q < PX; ++q) m = max_abs(m, hi[r][q]);
-        m = wave_max(m);
-        if (lane == 0) red2[par2 * NW + w] = m;
-        __syncthreads();
-        T g = 0;
-        for (int i = 0; i < NW; ++i) g = max_abs(g, red2[par2 * NW + i]);
-        return uniform(g);
+            for (int q = 0; q < PX; ++q) mx = max_abs(mx, hi[r][q]);
+        mx = wave_max_dpp(mx);
+        if (lane == 0) red2[par2 * NW + w] = mx;
     };
 
     int sub_par = 0;
-    T unorm = state_norm(sub_par);
-    sub_par ^= 1;
+    post_state_norm(sub_par);
     int tpar = 0;
     int pflag = 0;
+    StopRule<T> rule(tol, 1.0f + 0x1p-10f);
 
     for (int k = 0; k < K; ++k) {
         const TableView tv{tables + ((size_t)p * K + k) * tbytes};
@@ -255,63 +293,65 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
         const double es = tv.es();
         pflag |= tv.flag();
         const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
-        auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
         int terms = 0;
         for (int sub = 0; sub < s; ++sub) {
-            T c[RJ][PX];
+            T A[RJ][PX], B[RJ][PX];
 #pragma unroll
             for (int r = 0; r < RJ; ++r)
 #pragma unroll
-                for (int q = 0; q < PX; ++q) c[r][q] = hi[r][q];
-            T c1 = unorm;
-            for (int j = 1; j <= m; ++j) {
-                halo.publish(tpar, w, lane, c);
+                for (int q = 0; q < PX; ++q) A[r][q] = hi[r][q];
+            if (m == 0) __syncthreads();
+            auto step = [&](T (&in)[RJ][PX], T (&out)[RJ][PX], int j) -> bool {
+                halo.publish(tpar, w, lane, in);
                 __syncthreads();
-                if (j > 1) {
-                    T c2 = 0, fn = 0;
+                if (j == 1) {
+                    rule.start(lds_max<T, NW>(red2 + sub_par * NW, 1));
+                } else {
                     const T* rr = red + (size_t)(tpar ^ 1) * NW * 2;
-                    for (int i = 0; i < NW; ++i) {
-                        c2 = max_abs(c2, rr[2 * i]);
-                        fn = max_abs(fn, rr[2 * i + 1]);
-                    }
-                    c2 = uniform(c2);
-                    fn = uniform(fn);
-                    if (c1 + c2 <= tol * fn) break;
-                    c1 = c2;
+                    if (rule.stop(lds_max<T, NW>(rr, 2), [&] { return lds_max<T, NW>(rr + 1, 2); }))
+                        return false;
                 }
                 T top[RH][PX], bot[RH][PX];
-                halo.fetch(tpar, w, lane, top, bot);
-                auto din = [&](int rr, int q) -> T {
-                    if (rr < 0) return top[rr + RH][q];
-                    if (rr >= RJ) return bot[rr - RJ][q];
-                    return c[rr][q];
-                };
-                T cn[RJ][PX];
-                apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX, T>(din, coef, lane, nx, cn);
+                const int hp = tpar;
+                auto fb = [&] { halo.fetch_bot(hp, w, lane, bot); };
+                auto ft = [&] { halo.fetch_top(hp, w, lane, top); };
+                auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
                 const T invj = uniform((float)(1.0 / (double)j));
                 T mc = 0, mf = 0;
-#pragma unroll
-                for (int r = 0; r < RJ; ++r)
+                // c_j = Y' c_{j-1} / j goes to `out`; F = hi + lo gains c_j (Kahan)
+                auto kahan = [&](int r, T (&y)[PX]) {
 #pragma unroll
                     for (int q = 0; q < PX; ++q) {
-                        const T x = cn[r][q] * invj;
-                        c[r][q] = x;
-                        // Kahan: F = hi + lo gains x
-                        const T y = x + lo[r][q];
-                        const T t = hi[r][q] + y;
-                        lo[r][q] = y - (t - hi[r][q]);
+                        const T x = y[q] * invj;
+                        y[q] = x;
+                        const T a = x + lo[r][q];
+                        const T t = hi[r][q] + a;
+                        lo[r][q] = a - (t - hi[r][q]);
                         hi[r][q] = t;
                         mc = max_abs(mc, x);
-                        mf = max_abs(mf, t);
                     }
-                mc = wave_max(mc);
-                mf = wave_max(mf);
+                };
+                apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(in, out, top, bot, fb, ft, coef,
+                                                                    lane, nx, kahan);
+                if (rule.wantf) {
+#pragma unroll
+                    for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                        for (int q = 0; q < PX; ++q) mf = max_abs(mf, hi[r][q]);
+                    mf = wave_max_dpp(mf);
+                }
+                mc = wave_max_dpp(mc);
                 if (lane == 0) {
                     red[(size_t)tpar * NW * 2 + 2 * w] = mc;
                     red[(size_t)tpar * NW * 2 + 2 * w + 1] = mf;
                 }
                 tpar ^= 1;
                 ++terms;
+                return true;
+            };
+            for (int j = 1; j <= m; j += 2) {
+                if (!step(A, B, j)) break;
+                if (j + 1 > m || !step(B, A, j + 1)) break;
             }
             // u = exp(mu/s) (hi + lo) in FP64, split again
 #pragma unroll
@@ -322,8 +362,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                     hi[r][q] = (float)u;
                     lo[r][q] = (float)(u - (double)hi[r][q]);
                 }
-            unorm = state_norm(sub_par);
             sub_par ^= 1;
+            post_state_norm(sub_par);
         }
         if (stats && threadIdx.x == 0) {
             stats[((size_t)p * K + k) * 2] = terms;

@@ -75,6 +75,44 @@ __device__ inline void dt_apply(const T (&y)[PX], T (&out)[PX]) {
     }
 }
 
+// Max over the 64 lanes of non-negative values with DPP row shifts and row
+// broadcasts (no LDS traffic); the result is returned wave-uniform (lane 63's
+// value read into scalar registers).
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_pull(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL,
+                                               ROWMASK, 0xf, CTRL < 0x140);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL,
+                                               ROWMASK, 0xf, CTRL < 0x140);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ inline float dpp_pull(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
+                                                      CTRL, ROWMASK, 0xf, CTRL < 0x140));
+}
+__device__ inline double lane63(double x) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline float lane63(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+// row_shr:1,2,4,8 leave each 16-lane row's maximum in its lane 15 (lanes
+// without a source read zero, harmless for non-negative values);
+// row_bcast:15 and row_bcast:31 then carry rows 0..2 into lane 63.
+template <class T>
+__device__ inline T wave_max_dpp(T x) {
+    x = max_abs(x, dpp_pull<0x111, 0xf>(x));
+    x = max_abs(x, dpp_pull<0x112, 0xf>(x));
+    x = max_abs(x, dpp_pull<0x114, 0xf>(x));
+    x = max_abs(x, dpp_pull<0x118, 0xf>(x));
+    x = max_abs(x, dpp_pull<0x142, 0xa>(x));
+    x = max_abs(x, dpp_pull<0x143, 0xc>(x));
+    return lane63(x);
+}
+
 template <int R0, int R1, int R2>
 struct Bands {
     static constexpr int RH = (R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2));
@@ -238,6 +276,131 @@ __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
         for (int q = 0; q < PX; ++q) d[r][q] = res[r][q];
 }
 
+// One application of the banded-Kronecker operator in "difference first" form,
+// from d into a separate output.  Because V_q acts along v and Dt along x,
+// V_q (x) Dt^q = (V_q (x) I)(I (x) Dt^q): each row's x differences e1 = Dt d and
+// e2 = Dt e1 (truncated to the grid) are formed once, and every output point is
+// a single FMA chain over the bands,
+//   y(j) = sum_b V0[j][b] d(j+b) + sum_b V1[j][b] e1(j+b) + sum_b V2[j][b] e2(j+b).
+// Rows are produced in the order RH .. RJ-1, then 0 .. RH-1, so the halo rows
+// (read from LDS by fetch_bot / fetch_top a few rows before their first use)
+// arrive while interior rows are computed.  Each row's coefficients are
+// requested one row ahead.  Row r of the result goes to emit(r, y), which may
+// rescale y before it is stored in out[r].  Rows beyond nv have zero
+// coefficients in the padded tables; points beyond nx stay zero because every
+// input is zero there.
+template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, class T,
+          class Coef, class FetchBot, class FetchTop, class Emit>
+__device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&top)[RH][PX],
+                                   T (&bot)[RH][PX], FetchBot fetch_bot, FetchTop fetch_top,
+                                   Coef coef, int lane, int nx, Emit emit) {
+    using BD = Bands<R0, R1, R2>;
+    constexpr int NB = BD::NB;
+    constexpr int A2 = QMAX >= 2 ? R2 : 0;                    // e2 rows needed ahead
+    constexpr int A1 = QMAX >= 1 ? (A2 > R1 ? A2 : R1) : 0;   // e1 rows needed ahead
+    static_assert(A1 <= RH && A2 <= RH, "halo narrower than the difference window");
+    static_assert(RJ >= 2 * RH + 1, "too few rows per wave for the halo width");
+    // first row of the first pass that reads a bottom halo row, and the fetch
+    // points two rows ahead of first use
+    constexpr int RB = RJ - (R0 > A1 ? R0 : A1);
+    constexpr int FB = (RB - 2 > RH) ? RB - 2 : RH;
+    constexpr int FT = (RJ - 2 > RH) ? RJ - 2 : RH;
+    auto din = [&](int rr, int q) -> T {
+        if (rr < 0) return top[rr + RH][q];
+        if (rr >= RJ) return bot[rr - RJ][q];
+        return d[rr][q];
+    };
+    T e1[RJ + 2 * RH][PX], e2[RJ + 2 * RH][PX];   // row rr at index rr + RH
+    auto make_e1 = [&](int rr) {
+        T v[PX];
+#pragma unroll
+        for (int q = 0; q < PX; ++q) v[q] = din(rr, q);
+        dt_apply<PX, T>(v, e1[rr + RH]);
+        if (!FULLX) {
+#pragma unroll
+            for (int q = 0; q < PX; ++q)
+                if (lane * PX + q >= nx) e1[rr + RH][q] = T(0);
+        }
+    };
+    auto make_e2 = [&](int rr) {
+        dt_apply<PX, T>(e1[rr + RH], e2[rr + RH]);
+        if (!FULLX) {
+#pragma unroll
+            for (int q = 0; q < PX; ++q)
+                if (lane * PX + q >= nx) e2[rr + RH][q] = T(0);
+        }
+    };
+    auto order = [](int i) { return i < RJ - RH ? i + RH : i - (RJ - RH); };
+    T cur[NB], nxt[NB];
+#pragma unroll
+    for (int e = 0; e < NB; ++e) cur[e] = coef(RH, e);
+    // differences for the start of the first pass (rows RH - A .. RH + A - 1)
+    if (QMAX >= 1) {
+#pragma unroll
+        for (int rr = RH - A1; rr < RH + A1; ++rr) make_e1(rr);
+    }
+    if (QMAX >= 2) {
+#pragma unroll
+        for (int rr = RH - A2; rr < RH + A2; ++rr) make_e2(rr);
+    }
+#pragma unroll
+    for (int i = 0; i < RJ; ++i) {
+        const int r = order(i);
+        if (i + 1 < RJ) {
+            const int rn = order(i + 1);
+#pragma unroll
+            for (int e = 0; e < NB; ++e) nxt[e] = coef(rn, e);
+        }
+        if (r == FB) fetch_bot();
+        if (r == FT) fetch_top();
+        __builtin_amdgcn_sched_barrier(0);
+        if (i == RJ - RH) {
+            // second pass: differences of the rows above the first pass
+            if (QMAX >= 1) {
+#pragma unroll
+                for (int rr = -A1; rr < RH - A1; ++rr) make_e1(rr);
+            }
+            if (QMAX >= 2) {
+#pragma unroll
+                for (int rr = -A2; rr < RH - A2; ++rr) make_e2(rr);
+            }
+        }
+        if (i < RJ - RH) {
+            if (QMAX >= 1) make_e1(r + A1);
+            if (QMAX >= 2) make_e2(r + A2);
+        }
+        T y[PX];
+#pragma unroll
+        for (int q = 0; q < PX; ++q) y[q] = cur[0] * din(r - R0, q);
+#pragma unroll
+        for (int b = -R0 + 1; b <= R0; ++b)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) y[q] = fma(cur[b + R0], din(r + b, q), y[q]);
+        if (QMAX >= 1) {
+#pragma unroll
+            for (int b = -R1; b <= R1; ++b)
+#pragma unroll
+                for (int q = 0; q < PX; ++q)
+                    y[q] = fma(cur[BD::O1 + b + R1], e1[r + b + RH][q], y[q]);
+        }
+        if (QMAX >= 2) {
+#pragma unroll
+            for (int b = -R2; b <= R2; ++b)
+#pragma unroll
+                for (int q = 0; q < PX; ++q)
+                    y[q] = fma(cur[BD::O2 + b + R2], e2[r + b + RH][q], y[q]);
+        }
+        emit(r, y);
+#pragma unroll
+        for (int q = 0; q < PX; ++q) out[r][q] = y[q];
+        if (i + 1 < RJ) {
+#pragma unroll
+            for (int e = 0; e < NB; ++e) cur[e] = nxt[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // LDS halo layout: halo[parity][wave + 1][slot][64*PX] for waves -1 .. NW; the
 // guard waves -1 and NW are zero rows (the zero boundary in v) so that every
 // fetch is unconditional.  Slots 0..RH-1 hold a wave's first RH rows, slots
@@ -266,6 +429,20 @@ struct Halo {
                 bot[q] = d[RJ - RH + s][q];
             }
         }
+    }
+    // rows -RH..-1 (from wave w-1)
+    __device__ void fetch_top(int par, int w, int lane, T (&top)[RH][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) top[s][q] = slot(par, w - 1, RH + s)[lane * PX + q];
+    }
+    // rows RJ..RJ+RH-1 (from wave w+1)
+    __device__ void fetch_bot(int par, int w, int lane, T (&bot)[RH][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) bot[s][q] = slot(par, w + 1, s)[lane * PX + q];
     }
     // rows -RH..-1 (from wave w-1) and RJ..RJ+RH-1 (from wave w+1)
     __device__ void fetch(int par, int w, int lane, T (&top)[RH][PX], T (&bot)[RH][PX]) const {
