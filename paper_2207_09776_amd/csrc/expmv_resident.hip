@@ -34,6 +34,7 @@
 #include <cmath>
 
 #include "kernel_common.h"
+#include "theta_table.h"   // MG_THETA_MMAX
 
 namespace {
 
@@ -75,13 +76,38 @@ struct StopRule {
     }
 };
 
+// Max over the NW per-wave partial maxima when lane l holds the entry of wave
+// l mod NW (NW a power of two <= 16): row shifts reduce lanes 0..NW-1 and lane
+// NW-1 holds the result.  With one LDS read per lane this keeps a single LDS
+// round trip between the barrier and the next term.
 template <class T, int NW>
-__device__ inline T lds_max(const T* v, int stride) {
-    T g = 0;
-#pragma unroll
-    for (int i = 0; i < NW; ++i) g = max_abs(g, v[i * stride]);
-    return uniform(g);
+__device__ inline T waves_max(T x) {
+    static_assert(NW >= 1 && NW <= 16 && (NW & (NW - 1)) == 0, "NW must be a power of two");
+    if (NW > 1) x = max_abs(x, dpp_pull<0x111, 0xf>(x));
+    if (NW > 2) x = max_abs(x, dpp_pull<0x112, 0xf>(x));
+    if (NW > 4) x = max_abs(x, dpp_pull<0x114, 0xf>(x));
+    if (NW > 8) x = max_abs(x, dpp_pull<0x118, 0xf>(x));
+    return lane_value<NW - 1>(x);
 }
+
+// 1/j! (FP64 chain) and 1/j (FP32 chain) for j <= 63, formed by the same
+// sequence of correctly rounded operations the chain would use at run time.
+struct FactorTables {
+    double inv_fact[64];
+    float inv_j[64];
+};
+constexpr FactorTables make_factor_tables() {
+    FactorTables t{};
+    t.inv_fact[0] = 1.0;
+    t.inv_j[0] = 1.0f;
+    for (int j = 1; j < 64; ++j) {
+        t.inv_fact[j] = t.inv_fact[j - 1] / (double)j;
+        t.inv_j[j] = (float)(1.0 / (double)j);
+    }
+    return t;
+}
+__constant__ FactorTables kFactors = make_factor_tables();
+static_assert(MG_THETA_MMAX < 64, "factor tables too short");
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
@@ -153,16 +179,17 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                 for (int q = 0; q < PX; ++q) A[r][q] = F[r][q];
             // a sub-step without terms still orders the state-norm slots
             if (m == 0) __syncthreads();
-            T fj = 1;
             // term j from `in` into `out`; false when the series stopped before it
             auto step = [&](T (&in)[RJ][PX], T (&out)[RJ][PX], int j) -> bool {
                 halo.publish(tpar, w, lane, in);
                 __syncthreads();
                 if (j == 1) {
-                    rule.start(lds_max<T, NW>(red2 + sub_par * NW, 1));
+                    rule.start(waves_max<T, NW>(red2[sub_par * NW + (lane & (NW - 1))]));
                 } else {
-                    const T* rr = red + (size_t)(tpar ^ 1) * NW * 2;
-                    if (rule.stop(lds_max<T, NW>(rr, 2), [&] { return lds_max<T, NW>(rr + 1, 2); }))
+                    // norms of the previous term (both read at once)
+                    const T* rr = red + (size_t)(tpar ^ 1) * NW * 2 + 2 * (lane & (NW - 1));
+                    const T cw = rr[0], fw = rr[1];
+                    if (rule.stop(waves_max<T, NW>(cw), [&] { return waves_max<T, NW>(fw); }))
                         return false;
                 }
                 T top[RH][PX], bot[RH][PX];
@@ -170,7 +197,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                 auto fb = [&] { halo.fetch_bot(hp, w, lane, bot); };
                 auto ft = [&] { halo.fetch_top(hp, w, lane, top); };
                 auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
-                fj /= (T)j;             // 1/j!
+                const T fj = kFactors.inv_fact[j];   // 1/j!
                 T mc = 0, mf = 0;
                 apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(
                     in, out, top, bot, fb, ft, coef, lane, nx, [&](int r, T (&y)[PX]) {
@@ -305,10 +332,12 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                 halo.publish(tpar, w, lane, in);
                 __syncthreads();
                 if (j == 1) {
-                    rule.start(lds_max<T, NW>(red2 + sub_par * NW, 1));
+                    rule.start(waves_max<T, NW>(red2[sub_par * NW + (lane & (NW - 1))]));
                 } else {
-                    const T* rr = red + (size_t)(tpar ^ 1) * NW * 2;
-                    if (rule.stop(lds_max<T, NW>(rr, 2), [&] { return lds_max<T, NW>(rr + 1, 2); }))
+                    // norms of the previous term (both read at once)
+                    const T* rr = red + (size_t)(tpar ^ 1) * NW * 2 + 2 * (lane & (NW - 1));
+                    const T cw = rr[0], fw = rr[1];
+                    if (rule.stop(waves_max<T, NW>(cw), [&] { return waves_max<T, NW>(fw); }))
                         return false;
                 }
                 T top[RH][PX], bot[RH][PX];
@@ -316,7 +345,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                 auto fb = [&] { halo.fetch_bot(hp, w, lane, bot); };
                 auto ft = [&] { halo.fetch_top(hp, w, lane, top); };
                 auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
-                const T invj = uniform((float)(1.0 / (double)j));
+                const T invj = kFactors.inv_j[j];
                 T mc = 0, mf = 0;
                 // c_j = Y' c_{j-1} / j goes to `out`; F = hi + lo gains c_j (Kahan)
                 auto kahan = [&](int r, T (&y)[PX]) {

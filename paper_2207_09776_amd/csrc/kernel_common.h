@@ -91,13 +91,15 @@ __device__ inline float dpp_pull(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x),
                                                       CTRL, ROWMASK, 0xf, CTRL < 0x140));
 }
-__device__ inline double lane63(double x) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), 63);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), 63);
+template <int L>
+__device__ inline double lane_value(double x) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), L);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), L);
     return __hiloint2double(hi, lo);
 }
-__device__ inline float lane63(float x) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+template <int L>
+__device__ inline float lane_value(float x) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), L));
 }
 // row_shr:1,2,4,8 leave each 16-lane row's maximum in its lane 15 (lanes
 // without a source read zero, harmless for non-negative values);
@@ -110,7 +112,7 @@ __device__ inline T wave_max_dpp(T x) {
     x = max_abs(x, dpp_pull<0x118, 0xf>(x));
     x = max_abs(x, dpp_pull<0x142, 0xa>(x));
     x = max_abs(x, dpp_pull<0x143, 0xc>(x));
-    return lane63(x);
+    return lane_value<63>(x);
 }
 
 template <int R0, int R1, int R2>
@@ -331,9 +333,13 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
         }
     };
     auto order = [](int i) { return i < RJ - RH ? i + RH : i - (RJ - RH); };
-    T cur[NB], nxt[NB];
+    // coefficients of the current row and of the next two (requested two rows
+    // ahead: a miss in the scalar cache costs more than one row of work)
+    T cur[NB], nxt[NB], nx2[NB];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) cur[e] = coef(RH, e);
+    for (int e = 0; e < NB; ++e) cur[e] = coef(order(0), e);
+#pragma unroll
+    for (int e = 0; e < NB; ++e) nxt[e] = coef(order(1), e);
     // differences for the start of the first pass (rows RH - A .. RH + A - 1)
     if (QMAX >= 1) {
 #pragma unroll
@@ -346,10 +352,10 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
 #pragma unroll
     for (int i = 0; i < RJ; ++i) {
         const int r = order(i);
-        if (i + 1 < RJ) {
-            const int rn = order(i + 1);
+        if (i + 2 < RJ) {
+            const int rn = order(i + 2);
 #pragma unroll
-            for (int e = 0; e < NB; ++e) nxt[e] = coef(rn, e);
+            for (int e = 0; e < NB; ++e) nx2[e] = coef(rn, e);
         }
         if (r == FB) fetch_bot();
         if (r == FT) fetch_top();
@@ -393,9 +399,10 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
         emit(r, y);
 #pragma unroll
         for (int q = 0; q < PX; ++q) out[r][q] = y[q];
-        if (i + 1 < RJ) {
 #pragma unroll
-            for (int e = 0; e < NB; ++e) cur[e] = nxt[e];
+        for (int e = 0; e < NB; ++e) {
+            cur[e] = nxt[e];
+            nxt[e] = nx2[e];
         }
         __builtin_amdgcn_sched_barrier(0);
     }
