@@ -45,7 +45,11 @@ EULER_FLOPS_PT = 2 * 5 + 1            # u + (dt B + dW A) u: 5 non-zeros per row
 # WRITE_SIZE (KiB per dispatch), scaled by the factors the same counters give
 # for a plain 1 GiB copy kernel (fetch x 2.000, write x 1.000).  Valid only for
 # the kernel source they were measured on: the key is a hash of that source.
-TRAFFIC = {}
+TRAFFIC = {
+    # (source hash, workload): (bytes read, bytes written) per launch;
+    # profiles/expmv_resident_counters_const-128-p1024-m2-k16.txt
+    ("d86f1243dd35ab4a", "const-128-p1024-m2-k16"): (167299 * 1024 * 2.000, 131122 * 1024 * 1.000),
+}
 
 
 def _kernel_source_hash():
