@@ -93,8 +93,19 @@ mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32
     if (e == hipSuccess) e = hipMalloc((void**)&ops->basis_dev, bytes);
     if (e == hipSuccess)
         e = hipMemcpy(ops->basis_dev, ops->basis_host.data(), bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && ops->ND > 0) {
+        const size_t xb = ops->xdiag_host.size() * sizeof(double);
+        const size_t sb = ops->xstat_host.size() * sizeof(double);
+        e = hipMalloc((void**)&ops->xdiag_dev, xb + sb);
+        if (e == hipSuccess)
+            e = hipMemcpy(ops->xdiag_dev, ops->xdiag_host.data(), xb, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(ops->xdiag_dev + ops->xdiag_host.size(), ops->xstat_host.data(), sb,
+                          hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         if (ops->basis_dev) (void)hipFree(ops->basis_dev);
+        if (ops->xdiag_dev) (void)hipFree(ops->xdiag_dev);
         delete ops;
         return hip_fail(e, "mg_build_operators");
     }
@@ -106,6 +117,10 @@ mg_status mg_free_operators(mg_ops* ops) {
     if (!ops) return MG_OK;
     hipError_t e = hipSuccess;
     if (ops->basis_dev) e = hipFree(ops->basis_dev);
+    if (ops->xdiag_dev) {
+        hipError_t e2 = hipFree(ops->xdiag_dev);
+        if (e == hipSuccess) e = e2;
+    }
     delete ops;
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_free_operators");
 }
@@ -144,7 +159,8 @@ Family family_of(const mg_ops* ops, int precision) {
     if (launch_expmv_resident(ops, nullptr, 0, 1, 1, nullptr, 0, nullptr, 0.0, precision, nullptr,
                               nullptr, nullptr, true) == hipSuccess)
         return Family::Resident;
-    if (coop_rows_per_group_member(ops->grid.nx) > 0) return Family::Coop;
+    // the cooperative kernel does not take x-dependent factors
+    if (coop_rows_per_group_member(ops->grid.nx) > 0 && ops->ND == 0) return Family::Coop;
     return Family::None;
 }
 }  // namespace
@@ -175,7 +191,9 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
     hipStream_t s = (hipStream_t)stream;
     const Family fam = family_of(ops, precision);
     if (fam == Family::None)
-        return mg_fail(MG_EUNSUPPORTED, "mg_magnus_expmv: no kernel for this grid size");
+        return mg_fail(MG_EUNSUPPORTED,
+                       ops->ND > 0 ? "mg_magnus_expmv: x-dependent coefficients need nx, nv <= 128"
+                                   : "mg_magnus_expmv: no kernel for this grid size");
     if (P == 0) return MG_OK;
     if (!coef || !u0 || !uT || !ws) return mg_fail(MG_EINVAL, "mg_magnus_expmv: NULL pointer");
     CoopPlan plan;

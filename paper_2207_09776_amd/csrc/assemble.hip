@@ -15,7 +15,11 @@
 // {-2..2}:   i'-2: a2,  i'-1: a1,  i': a0 + a2 * diag(Dt^2)_{i'},  i'+1: -a1,
 // i'+2: a2, with a_q = V_q[j][j' - j] (entries outside the grid are absent).
 // Columns i' = 2 .. nx-3 share one pattern, so the classes
-// i' in {0, 1, 2, nx-3, nx-2, nx-1} cover all columns.
+// i' in {0, 1, 2, nx-3, nx-2, nx-1} cover all columns.  Terms W_t (x) diag(a_t)
+// (x-dependent coefficients) add w_t a_t(i') to the entry in row i'; there the
+// sum uses |c + sum_t w_t m_t| + sum_t |w_t| h_t with m_t, h_t the midpoint and
+// half-width of the values of a_t, an upper bound of the exact column sum, so
+// (m, s) stay admissible (at worst s is larger than needed).
 
 #include <cmath>
 
@@ -35,6 +39,8 @@ struct AsmArgs {
     int f32;                   // rows in FP32 (compensated form) instead of FP64
     int nx, nv, nv_pad, K, NBP, nact;
     int R0, R1, R2;
+    int ND, RW;                // x-dependent factors (0: none) and their band radius
+    const double* xstat;       // per factor {sum, midpoint, half-width, 0}
     int use24;                 // theta table for 2^-24 instead of 2^-53
 };
 
@@ -70,14 +76,17 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
     const int64_t pk = blockIdx.x;
     const double* c = a.coef + pk * 6;
     const int t = threadIdx.x;
-    const int o0 = 0, o1 = 2 * a.R0 + 1, o2 = o1 + 2 * a.R1 + 1;
+    const int o0 = 0, o1 = 2 * a.R0 + 1, o2 = o1 + 2 * a.R1 + 1, o3 = o2 + 2 * a.R2 + 1;
+    const int wl = 2 * a.RW + 1;
     const int nx = a.nx, nv = a.nv;
 
-    // trace: sum_j (nx * V0[j][0] + tr(Dt^2) * V2[j][0])
+    // trace: sum_j (nx * V0[j][0] + tr(Dt^2) * V2[j][0] + sum_t W_t[j][0] * sum_i a_t(i))
     const double trDt2 = nx >= 2 ? -(2.0 * nx - 2.0) : 0.0;
     double tr = 0.0;
-    for (int j = t; j < nv; j += kThreads)
+    for (int j = t; j < nv; j += kThreads) {
         tr += nx * coeff(a, c, j, o0 + a.R0) + trDt2 * coeff(a, c, j, o2 + a.R2);
+        for (int f = 0; f < a.ND; ++f) tr += coeff(a, c, j, o3 + f * wl + a.RW) * a.xstat[4 * f];
+    }
     tr = block_reduce(tr, red, false);
     const double mu = tr / ((double)nx * nv);
 
@@ -89,16 +98,22 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
         const int ip = cls[idx % 6];
         if (ip < 0 || ip >= nx) continue;
         double sum = 0.0;
-        const int R = max(a.R0, max(a.R1, a.R2));
+        const int R = max(max(a.R0, a.R1), max(a.R2, a.ND > 0 ? a.RW : 0));
         for (int j = max(0, jp - R); j <= min(nv - 1, jp + R); ++j) {
             const int b = jp - j;
             const double a0 = (b >= -a.R0 && b <= a.R0) ? coeff(a, c, j, o0 + b + a.R0) : 0.0;
             const double a1 = (b >= -a.R1 && b <= a.R1) ? coeff(a, c, j, o1 + b + a.R1) : 0.0;
             const double a2 = (b >= -a.R2 && b <= a.R2) ? coeff(a, c, j, o2 + b + a.R2) : 0.0;
-            const double d0 = a0 - (b == 0 ? mu : 0.0);
+            double d0 = a0 - (b == 0 ? mu : 0.0), spread = 0.0;
+            if (b >= -a.RW && b <= a.RW)
+                for (int f = 0; f < a.ND; ++f) {
+                    const double w = coeff(a, c, j, o3 + f * wl + b + a.RW);
+                    d0 += w * a.xstat[4 * f + 1];
+                    spread += fabs(w) * a.xstat[4 * f + 2];
+                }
             if (ip - 2 >= 0) sum += fabs(a2);
             if (ip - 1 >= 0) sum += fabs(a1);
-            sum += fabs(d0 + a2 * dt2_diag(ip, nx));
+            sum += fabs(d0 + a2 * dt2_diag(ip, nx)) + spread;
             if (ip + 1 < nx) sum += fabs(a1);
             if (ip + 2 < nx) sum += fabs(a2);
         }
@@ -176,6 +191,9 @@ hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int
     a.R0 = ops->R[0];
     a.R1 = ops->R[1];
     a.R2 = ops->R[2];
+    a.ND = ops->ND;
+    a.RW = ops->RW;
+    a.xstat = ops->ND > 0 ? ops->xdiag_dev + (size_t)ops->ND * ops->grid.nx : nullptr;
     a.use24 = tol >= 0x1p-24 ? 1 : 0;
     const int64_t blocks = P * K;
     hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);

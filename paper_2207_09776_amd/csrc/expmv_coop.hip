@@ -531,6 +531,8 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
                              const CoopPlan& plan, hipStream_t s) {
     const void* fn = nullptr;
     size_t lds = 0;
+    // this kernel reads tables without x-dependent factors
+    if (ops->ND != 0) return hipErrorInvalidValue;
     hipError_t e = coop_info(ops, precision, &fn, &lds);
     if (e != hipSuccess) return e;
     CoopArgs a;

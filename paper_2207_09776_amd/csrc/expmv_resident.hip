@@ -109,15 +109,15 @@ constexpr FactorTables make_factor_tables() {
 __constant__ FactorTables kFactors = make_factor_tables();
 static_assert(MG_THETA_MMAX < 64, "factor tables too short");
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, double tol,
-    int32_t* __restrict__ stats, int32_t* __restrict__ flags) {
+    int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag) {
     using T = double;
     using BD = Bands<R0, R1, R2>;
-    constexpr int RH = BD::RH > 0 ? BD::RH : 1;
-    constexpr int NBP = BD::NBP;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, ND>();
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
@@ -133,6 +133,16 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     const size_t N = (size_t)nx * nv;
     if (threadIdx.x == 0) *sflag = 0;
     halo.zero_guards(threadIdx.x, 64 * NW);
+    // x-dependent factors at this lane's points (zero beyond nx)
+    constexpr int NDX = ND > 0 ? ND : 1;
+    T xa[NDX][PX];
+#pragma unroll
+    for (int t = 0; t < NDX; ++t)
+#pragma unroll
+        for (int q = 0; q < PX; ++q) {
+            const int i = lane * PX + q;
+            xa[t][q] = (ND > 0 && i < nx) ? (T)xdiag[(size_t)t * nx + i] : T(0);
+        }
 
     T F[RJ][PX];
     {
@@ -199,8 +209,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                 auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
                 const T fj = kFactors.inv_fact[j];   // 1/j!
                 T mc = 0, mf = 0;
-                apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(
-                    in, out, top, bot, fb, ft, coef, lane, nx, [&](int r, T (&y)[PX]) {
+                apply_rows_any<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, T>(
+                    in, out, top, bot, fb, ft, coef, xa, lane, nx, [&](int r, T (&y)[PX]) {
 #pragma unroll
                         for (int q = 0; q < PX; ++q) {
                             F[r][q] = fma(y[q], fj, F[r][q]);
@@ -258,15 +268,15 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
 }
 
 // Compensated FP32 form (see the file header).
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
     const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, float tol,
-    int32_t* __restrict__ stats, int32_t* __restrict__ flags) {
+    int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag) {
     using T = float;
     using BD = Bands<R0, R1, R2>;
-    constexpr int RH = BD::RH > 0 ? BD::RH : 1;
-    constexpr int NBP = BD::NBP;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, ND>();
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
@@ -282,6 +292,16 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
     const size_t N = (size_t)nx * nv;
     if (threadIdx.x == 0) *sflag = 0;
     halo.zero_guards(threadIdx.x, 64 * NW);
+    // x-dependent factors at this lane's points (zero beyond nx)
+    constexpr int NDX = ND > 0 ? ND : 1;
+    T xa[NDX][PX];
+#pragma unroll
+    for (int t = 0; t < NDX; ++t)
+#pragma unroll
+        for (int q = 0; q < PX; ++q) {
+            const int i = lane * PX + q;
+            xa[t][q] = (ND > 0 && i < nx) ? (T)xdiag[(size_t)t * nx + i] : T(0);
+        }
 
     // F = hi + lo (hi carries the FP32 value, lo the compensation)
     T hi[RJ][PX], lo[RJ][PX];
@@ -360,8 +380,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                         mc = max_abs(mc, x);
                     }
                 };
-                apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(in, out, top, bot, fb, ft, coef,
-                                                                    lane, nx, kahan);
+                apply_rows_any<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, T>(
+                    in, out, top, bot, fb, ft, coef, xa, lane, nx, kahan);
                 if (rule.wantf) {
 #pragma unroll
                     for (int r = 0; r < RJ; ++r)
@@ -419,14 +439,15 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
 }
 
 // Euler-Maruyama: u <- u + (dt B + dW_n A) u for n = 0..NE-1 (FP64).
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
 __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     const double* __restrict__ basis, int nx, int nv, int nv_pad, double* __restrict__ u,
-    const double* __restrict__ dWE, int NE, double dt, int32_t* __restrict__ flags) {
+    const double* __restrict__ dWE, int NE, double dt, int32_t* __restrict__ flags,
+    const double* __restrict__ xdiag) {
     using T = double;
     using BD = Bands<R0, R1, R2>;
-    constexpr int RH = BD::RH > 0 ? BD::RH : 1;
-    constexpr int NBP = BD::NBP;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, ND>();
     extern __shared__ double lds[];
     Halo<PX, RJ, NW, RH, T> halo{lds};
     int* sflag = reinterpret_cast<int*>(lds + halo_bytes<PX, NW, RH, T>() / sizeof(T));
@@ -439,6 +460,16 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     const size_t N = (size_t)nx * nv;
     if (threadIdx.x == 0) *sflag = 0;
     halo.zero_guards(threadIdx.x, 64 * NW);
+    // x-dependent factors at this lane's points (zero beyond nx)
+    constexpr int NDX = ND > 0 ? ND : 1;
+    T xa[NDX][PX];
+#pragma unroll
+    for (int t = 0; t < NDX; ++t)
+#pragma unroll
+        for (int q = 0; q < PX; ++q) {
+            const int i = lane * PX + q;
+            xa[t][q] = (ND > 0 && i < nx) ? (T)xdiag[(size_t)t * nx + i] : T(0);
+        }
 
     T d[RJ][PX];
     double* src = u + (size_t)p * N;
@@ -469,6 +500,28 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
         };
         T dn[RJ][PX];
         apply_operator<PX, RJ, R0, R1, R2, QMAX, FULLX, T>(din, coef, lane, nx, dn);
+        if constexpr (ND > 0) {
+            // x-dependent factors: dn += a_t(x) * sum_b W_t[j][b] d(j+b)
+            constexpr int WL = 2 * MG_XDIAG_RADIUS + 1;
+            constexpr int NBM = BD::NB;
+#pragma unroll
+            for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                for (int t = 0; t < ND; ++t) {
+                    T z[PX];
+#pragma unroll
+                    for (int q = 0; q < PX; ++q) z[q] = T(0);
+#pragma unroll
+                    for (int b = 0; b < WL; ++b)
+#pragma unroll
+                        for (int q = 0; q < PX; ++q)
+                            z[q] = fma(coef(r, NBM + t * WL + b), din(r - MG_XDIAG_RADIUS + b, q), z[q]);
+#pragma unroll
+                    for (int q = 0; q < PX; ++q) dn[r][q] = fma(xa[t][q], z[q], dn[r][q]);
+                    // one row and factor at a time (the coefficient sums are VALU work)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+        }
 #pragma unroll
         for (int r = 0; r < RJ; ++r)
 #pragma unroll
@@ -513,39 +566,45 @@ bool pick_shape(int nx, int nv, Shape& sh) {
     return false;
 }
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
 hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P, int K,
                      const double* u0, int bc, double* uT, double tol, int precision,
                      int32_t* stats, int32_t* flags, hipStream_t s) {
-    constexpr int RH = Bands<R0, R1, R2>::RH > 0 ? Bands<R0, R1, R2>::RH : 1;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    // the tables must have the row layout the kernel reads
+    if (ops->NBP != table_stride<R0, R1, R2, ND>()) return hipErrorInvalidValue;
     if (precision == MG_FP64) {
         constexpr size_t lds = resident_lds_bytes<PX, NW, RH, double>();
-        auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
+        auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables, tbytes, K,
-                           ops->grid.nx, ops->grid.nv, u0, bc, uT, tol, stats, flags);
+                           ops->grid.nx, ops->grid.nv, u0, bc, uT, tol, stats, flags,
+                           ops->xdiag_dev);
     } else {
         constexpr size_t lds = resident_lds_bytes<PX, NW, RH, float>();
-        auto kern = expmv_resident_f32c_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
+        auto kern = expmv_resident_f32c_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables, tbytes, K,
-                           ops->grid.nx, ops->grid.nv, u0, bc, uT, (float)tol, stats, flags);
+                           ops->grid.nx, ops->grid.nv, u0, bc, uT, (float)tol, stats, flags,
+                           ops->xdiag_dev);
     }
     return hipGetLastError();
 }
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
 hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE, int NE,
                      double dt, int32_t* flags, hipStream_t s) {
-    constexpr int RH = Bands<R0, R1, R2>::RH > 0 ? Bands<R0, R1, R2>::RH : 1;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    if (ops->NBP != table_stride<R0, R1, R2, ND>()) return hipErrorInvalidValue;
     constexpr size_t lds = halo_bytes<PX, NW, RH, double>() + 16;
-    auto kern = euler_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX>;
+    auto kern = euler_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, ops->basis_dev,
-                       ops->grid.nx, ops->grid.nv, ops->nv_pad, u, dWE, NE, dt, flags);
+                       ops->grid.nx, ops->grid.nv, ops->nv_pad, u, dWE, NE, dt, flags,
+                       ops->xdiag_dev);
     return hipGetLastError();
 }
 
@@ -554,10 +613,15 @@ hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE,
 // constant-coefficient Langevin operator, (2,1,1,2) its order 3, (3,3,3,2)
 // v-dependent coefficients.  B and A (Euler) only carry Dt^0 and Dt^1.
 #define MG_FOR_SHAPE(PX, RJ, NW, FULLX, CALL)                                                  \
-    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX); \
-    if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX); \
+    if (ops->ND > 0) {                                                                         \
+        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, MG_MAX_XDIAG); \
+        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG); \
+        return hipErrorInvalidValue;                                                           \
+    }                                                                                          \
+    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, 0); \
+    if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX, 0); \
     return hipErrorInvalidValue;
 
 #define MG_DISPATCH(CALL)                                                                      \
@@ -588,8 +652,8 @@ hipError_t launch_expmv_resident(const mg_ops* ops, const char* tables, size_t t
     if (dry_run) return hipSuccess;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-#define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX)                                       \
-    run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX>(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, \
+#define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX, ND)                                   \
+    run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX, ND>(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, \
                                               tol, precision, stats, flags, s)
     MG_DISPATCH(MG_CALL_EXPMV)
 #undef MG_CALL_EXPMV
@@ -603,8 +667,8 @@ hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const 
     if (dry_run) return hipSuccess;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-#define MG_CALL_EULER(PX, RJ, NW, R0, R1, R2, QM, FX) \
-    run_euler<PX, RJ, NW, R0, R1, R2, 1, FX>(ops, u, P, dWE, NE, dt, flags, s)
+#define MG_CALL_EULER(PX, RJ, NW, R0, R1, R2, QM, FX, ND) \
+    run_euler<PX, RJ, NW, R0, R1, R2, 1, FX, ND>(ops, u, P, dWE, NE, dt, flags, s)
     MG_DISPATCH(MG_CALL_EULER)
 #undef MG_CALL_EULER
 }

@@ -408,6 +408,90 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
     }
 }
 
+// apply_split with x-dependent factors: after the V bands, every factor
+// W_t (x) diag(a_t) adds a_t(x) * sum_b W_t[j][b] d(j+b) to the row, with
+// a_t at this lane's points in xa.  The W bands follow the V bands in the table
+// row (NBM coefficients); their coefficients are requested at the start of the
+// row.  RH must cover RW.
+template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, int RW,
+          class T, class Coef, class FetchBot, class FetchTop, class Emit>
+__device__ inline void apply_split_x(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&top)[RH][PX],
+                                     T (&bot)[RH][PX], FetchBot fetch_bot, FetchTop fetch_top,
+                                     Coef coef, const T (&xa)[ND][PX], int lane, int nx,
+                                     Emit emit) {
+    constexpr int NBM = Bands<R0, R1, R2>::NB;
+    constexpr int WL = 2 * RW + 1;
+    static_assert(RW <= RH, "halo narrower than the x-dependent factors");
+    auto din = [&](int rr, int q) -> T {
+        if (rr < 0) return top[rr + RH][q];
+        if (rr >= RJ) return bot[rr - RJ][q];
+        return d[rr][q];
+    };
+    // the first RB row that reads a bottom halo row, with the W bands included
+    constexpr int RWB = RW > R0 ? RW : R0;
+    apply_split<PX, RJ, (RWB > R0 ? RWB : R0), R1, R2, QMAX, FULLX, RH, T>(
+        d, out, top, bot, fetch_bot, fetch_top,
+        [&](int r, int e) -> T {
+            // the widened V0 band of apply_split: pad with zeros around V0
+            constexpr int PAD = (RWB > R0 ? RWB : R0) - R0;
+            constexpr int O1W = 2 * (R0 + PAD) + 1;
+            if (e < O1W) {
+                const int b = e - PAD;
+                return (b >= 0 && b < 2 * R0 + 1) ? coef(r, b) : T(0);
+            }
+            return coef(r, e - 2 * PAD);
+        },
+        lane, nx, [&](int r, T (&y)[PX]) {
+            T w[ND][WL];
+#pragma unroll
+            for (int t = 0; t < ND; ++t)
+#pragma unroll
+                for (int b = 0; b < WL; ++b) w[t][b] = coef(r, NBM + t * WL + b);
+#pragma unroll
+            for (int t = 0; t < ND; ++t) {
+                T z[PX];
+#pragma unroll
+                for (int q = 0; q < PX; ++q) z[q] = w[t][0] * din(r - RW, q);
+#pragma unroll
+                for (int b = 1; b < WL; ++b)
+#pragma unroll
+                    for (int q = 0; q < PX; ++q) z[q] = fma(w[t][b], din(r - RW + b, q), z[q]);
+#pragma unroll
+                for (int q = 0; q < PX; ++q) y[q] = fma(xa[t][q], z[q], y[q]);
+            }
+            emit(r, y);
+        });
+}
+
+// Halo rows per side a kernel shape needs: the widest band, including the
+// bands of the x-dependent factors when there are any.
+template <int R0, int R1, int R2, int ND>
+constexpr int halo_rows() {
+    constexpr int rh = Bands<R0, R1, R2>::RH > 0 ? Bands<R0, R1, R2>::RH : 1;
+    return (ND > 0 && MG_XDIAG_RADIUS > rh) ? MG_XDIAG_RADIUS : rh;
+}
+
+// Coefficients per table row (padded to an even count): the V bands, then the
+// bands of the x-dependent factors.
+template <int R0, int R1, int R2, int ND>
+constexpr int table_stride() {
+    return (Bands<R0, R1, R2>::NB + ND * (2 * MG_XDIAG_RADIUS + 1) + 1) & ~1;
+}
+
+// apply_split, or apply_split_x when the operator has x-dependent factors.
+template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, class T,
+          int NDX, class Coef, class FetchBot, class FetchTop, class Emit>
+__device__ inline void apply_rows_any(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&top)[RH][PX],
+                                      T (&bot)[RH][PX], FetchBot fb, FetchTop ft, Coef coef,
+                                      const T (&xa)[NDX][PX], int lane, int nx, Emit emit) {
+    if constexpr (ND == 0)
+        apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, out, top, bot, fb, ft, coef, lane, nx,
+                                                            emit);
+    else
+        apply_split_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
+            d, out, top, bot, fb, ft, coef, xa, lane, nx, emit);
+}
+
 // LDS halo layout: halo[parity][wave + 1][slot][64*PX] for waves -1 .. NW; the
 // guard waves -1 and NW are zero rows (the zero boundary in v) so that every
 // fetch is unconditional.  Slots 0..RH-1 hold a wave's first RH rows, slots

@@ -18,9 +18,16 @@
 // into V_{l,q}.  V_{l,q} is an nv x nv band matrix with radius R[q]; row j is
 // stored as 2R[q]+1 entries for columns j-R[q] .. j+R[q].  The bands of the
 // three q are concatenated per row: NB = sum_q (2R[q]+1) doubles, padded to NBP.
+//
+// Coefficients that depend on x add terms W_{l,t} (x) diag(a_t) (t < ND, the
+// x vectors a_t shared by all l); their bands (radius RW) follow the three V
+// bands in each row, so NB = sum_q (2R[q]+1) + ND (2RW+1).  ND is 0 or
+// MG_MAX_XDIAG (unused factors are zero).
 // ---------------------------------------------------------------------------
 constexpr int MG_NBASIS = 6;
 constexpr int MG_HDR = 8;          // table header entries (doubles)
+constexpr int MG_MAX_XDIAG = 4;    // x-dependent factors the kernels take
+constexpr int MG_XDIAG_RADIUS = 2; // band radius of their v factors
 
 struct mg_ops {
     mg_grid grid;
@@ -30,9 +37,13 @@ struct mg_ops {
     int NB, NBP;                   // coefficients per row, padded row stride
     int nactive;                   // basis matrices used by `order` (2, 4 or 6)
     int nv_pad;                    // table rows: nv rounded up to the kernel's rows (zeros)
+    int ND = 0, RW = 0;            // x-dependent factors and their band radius
     // basis tables, host copy and device copy: [MG_NBASIS][nv_pad][NBP]
     std::vector<double> basis_host;
     double* basis_dev = nullptr;
+    // x vectors a_t [ND][nx] and per factor {sum, midpoint, half-width, 0}
+    std::vector<double> xdiag_host, xstat_host;
+    double* xdiag_dev = nullptr;   // xdiag, then xstat, in one allocation
     int device = 0;
 };
 

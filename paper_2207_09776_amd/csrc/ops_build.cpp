@@ -11,6 +11,15 @@
 // D^x ((V (x) D^p)(W (x) D^q) = VW (x) D^{p+q}), so A^2 and the commutators of
 // eq. (MagnusFormulas) are formed exactly, as products of the truncated
 // matrices, by 1-D banded products.  Powers of D^x up to 2 occur.
+//
+// Coefficients of the terms without an x derivative (H, F^v, G^vv in B;
+// Sigma, Sigma^v in A) may also depend on x.  Such a coefficient grid z(x, v)
+// is written exactly (to rounding) as a short sum sum_t b_t(v) a_t(x) by a
+// cross decomposition with complete pivoting, so diag(vec Z) = sum_t
+// diag(b_t) (x) diag(a_t): the operators gain terms W (x) diag(a) next to the
+// V_q (x) D^q terms.  Products stay of that form as long as no power of D^x
+// meets a non-constant diag(a) (diag(a) diag(b) = diag(ab)); otherwise the
+// build reports the combination as unsupported.
 
 #include <algorithm>
 #include <cmath>
@@ -85,34 +94,137 @@ Band second_difference(int n, double d) {
     return D;
 }
 
-// sum_{q=0..2} V[q] (x) (D^x)^q
-struct KOp {
-    Band V[3];
-    explicit KOp(int nv) { for (auto& b : V) b = band_zero(nv); }
+bool band_is_zero(const Band& B) {
+    return std::all_of(B.a.begin(), B.a.end(), [](double v) { return v == 0.0; });
+}
+
+// Registry of the x vectors of diagonal x-factors diag(a); equal vectors share
+// one entry, so products of factors can be matched exactly.
+struct XReg {
+    std::vector<std::vector<double>> vecs;
+    int find_or_add(const std::vector<double>& a) {
+        for (size_t k = 0; k < vecs.size(); ++k)
+            if (vecs[k] == a) return (int)k;
+        vecs.push_back(a);
+        return (int)vecs.size() - 1;
+    }
 };
 
-bool kop_mul(const KOp& X, const KOp& Y, KOp& out) {
+// sum_{q=0..2} V[q] (x) (D^x)^q + sum_k W[k] (x) diag(xreg.vecs[id[k]])
+struct KOp {
+    Band V[3];
+    std::vector<Band> W;
+    std::vector<int> id;
+    explicit KOp(int nv) { for (auto& b : V) b = band_zero(nv); }
+    void add_w(int xid, const Band& B) {
+        for (size_t k = 0; k < id.size(); ++k)
+            if (id[k] == xid) {
+                W[k] = band_axpby(1.0, W[k], 1.0, B);
+                return;
+            }
+        id.push_back(xid);
+        W.push_back(B);
+    }
+};
+
+// Product of two factored operators; false (with a reason) when a power of
+// D^x meets a non-constant diagonal x-factor, which this form cannot hold.
+bool kop_mul(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
     int nv = X.V[0].n;
     KOp Z(nv);
     for (int p = 0; p < 3; ++p)
         for (int q = 0; q < 3; ++q) {
-            bool xz = std::all_of(X.V[p].a.begin(), X.V[p].a.end(), [](double v) { return v == 0.0; });
-            bool yz = std::all_of(Y.V[q].a.begin(), Y.V[q].a.end(), [](double v) { return v == 0.0; });
-            if (xz || yz) continue;
-            if (p + q > 2) return false;
-            Z.V[p + q] = band_axpby(1.0, Z.V[p + q], 1.0, band_mul(X.V[p], Y.V[q]));
+            if (band_is_zero(X.V[p]) || band_is_zero(Y.V[q])) continue;
+            Band P = band_mul(X.V[p], Y.V[q]);
+            if (band_is_zero(P)) continue;
+            if (p + q > 2) { why = "x-derivative power above 2 in the Magnus basis"; return false; }
+            Z.V[p + q] = band_axpby(1.0, Z.V[p + q], 1.0, P);
         }
+    for (size_t k = 0; k < Y.W.size(); ++k)
+        for (int p = 0; p < 3; ++p) {
+            if (band_is_zero(X.V[p]) || band_is_zero(Y.W[k])) continue;
+            Band P = band_mul(X.V[p], Y.W[k]);
+            if (band_is_zero(P)) continue;
+            if (p > 0) {
+                why = "an x derivative meets an x-dependent coefficient in the Magnus basis";
+                return false;
+            }
+            Z.add_w(Y.id[k], P);
+        }
+    for (size_t k = 0; k < X.W.size(); ++k) {
+        for (int q = 0; q < 3; ++q) {
+            if (band_is_zero(X.W[k]) || band_is_zero(Y.V[q])) continue;
+            Band P = band_mul(X.W[k], Y.V[q]);
+            if (band_is_zero(P)) continue;
+            if (q > 0) {
+                why = "an x derivative meets an x-dependent coefficient in the Magnus basis";
+                return false;
+            }
+            Z.add_w(X.id[k], P);
+        }
+        for (size_t m = 0; m < Y.W.size(); ++m) {
+            if (band_is_zero(X.W[k]) || band_is_zero(Y.W[m])) continue;
+            Band P = band_mul(X.W[k], Y.W[m]);
+            if (band_is_zero(P)) continue;
+            const std::vector<double>& a = xr.vecs[X.id[k]];
+            const std::vector<double>& b = xr.vecs[Y.id[m]];
+            std::vector<double> ab(a.size());
+            for (size_t i = 0; i < a.size(); ++i) ab[i] = a[i] * b[i];
+            Z.add_w(xr.find_or_add(ab), P);
+        }
+    }
     out = Z;
     return true;
 }
 
-bool kop_comm(const KOp& X, const KOp& Y, KOp& out) {
-    KOp XY(X.V[0].n), YX(X.V[0].n);
-    if (!kop_mul(X, Y, XY) || !kop_mul(Y, X, YX)) return false;
-    KOp Z(X.V[0].n);
+bool kop_comm(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
+    const int nv = X.V[0].n;
+    KOp XY(nv), YX(nv);
+    if (!kop_mul(X, Y, xr, XY, why) || !kop_mul(Y, X, xr, YX, why)) return false;
+    KOp Z(nv);
     for (int q = 0; q < 3; ++q) Z.V[q] = band_axpby(1.0, XY.V[q], -1.0, YX.V[q]);
+    for (size_t k = 0; k < XY.W.size(); ++k) Z.add_w(XY.id[k], XY.W[k]);
+    for (size_t k = 0; k < YX.W.size(); ++k) Z.add_w(YX.id[k], band_axpby(-1.0, YX.W[k], 0.0, YX.W[k]));
     out = Z;
     return true;
+}
+
+// Exact low-rank form of a coefficient grid z[j][i] (v row j, x column i):
+// z = sum_t b_t(v) a_t(x), by cross approximation with complete pivoting
+// (Gaussian elimination on the residual, largest entry first), stopped when
+// the residual is below 1e-14 of max|z| (the rounding level of the operator).
+// For the smooth coefficients of the workloads the rank is the number of
+// separable terms of the formula.  The x vectors are scaled to a largest
+// entry of 1.
+bool low_rank(const double* z, int nx, int nv, int max_rank, std::vector<std::vector<double>>& bs,
+              std::vector<std::vector<double>>& as) {
+    std::vector<double> R(z, z + (size_t)nx * nv);
+    double zmax = 0.0;
+    for (double v : R) zmax = std::max(zmax, std::fabs(v));
+    bs.clear();
+    as.clear();
+    if (zmax == 0.0) return true;
+    for (int t = 0; t <= max_rank; ++t) {
+        size_t piv = 0;
+        double pmax = 0.0;
+        for (size_t k = 0; k < R.size(); ++k)
+            if (std::fabs(R[k]) > pmax) { pmax = std::fabs(R[k]); piv = k; }
+        if (pmax <= 1e-14 * zmax) return true;
+        if (t == max_rank) return false;
+        const int jp = (int)(piv / nx), ip = (int)(piv % nx);
+        std::vector<double> a(nx), b(nv);
+        double amax = 0.0;
+        for (int i = 0; i < nx; ++i) { a[i] = R[(size_t)jp * nx + i]; amax = std::max(amax, std::fabs(a[i])); }
+        const double sa = 1.0 / amax;
+        for (int i = 0; i < nx; ++i) a[i] *= sa;
+        // b_j = R[j][ip] / a[ip] so that b a^T reproduces row jp and column ip
+        for (int j = 0; j < nv; ++j) b[j] = R[(size_t)j * nx + ip] / a[ip];
+        for (int j = 0; j < nv; ++j)
+            for (int i = 0; i < nx; ++i) R[(size_t)j * nx + i] -= b[j] * a[i];
+        bs.push_back(b);
+        as.push_back(a);
+    }
+    return false;
 }
 
 // Coefficient that must depend on v only: returns per-row values or fails.
@@ -145,44 +257,91 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     const size_t N = (size_t)nx * nv;
     if (!all_zero(cf->gxx, N) || !all_zero(cf->sx, N))
         return mg_fail(MG_EUNSUPPORTED, "g^xx and sigma^x must be zero in this build");
-    const double* vonly[7] = {cf->h, cf->fx, cf->fv, cf->gxv, cf->gvv, cf->sig, cf->sv};
-    const char* names[7] = {"h", "fx", "fv", "gxv", "gvv", "sig", "sv"};
-    std::vector<double> c[7];
-    bool nz[7];
-    for (int t = 0; t < 7; ++t)
-        if (!v_only(vonly[t], nx, nv, c[t], nz[t]))
+    // Coefficients of the D^x terms must depend on v only; the others may
+    // depend on x through the low-rank form.
+    enum { H, FX, FV, GXV, GVV, SIG, SV, NCOEF };
+    const double* fields[NCOEF] = {cf->h, cf->fx, cf->fv, cf->gxv, cf->gvv, cf->sig, cf->sv};
+    const char* names[NCOEF] = {"h", "fx", "fv", "gxv", "gvv", "sig", "sv"};
+    const bool x_allowed[NCOEF] = {true, false, true, false, true, true, true};
+    std::vector<double> c[NCOEF];                 // v-only part of each coefficient
+    std::vector<std::vector<double>> xb[NCOEF];  // x-dependent terms: b_t(v) ...
+    std::vector<int> xid[NCOEF];                 // ... times diag(a_t), registry ids
+    XReg xr;
+    for (int t = 0; t < NCOEF; ++t) {
+        bool nz;
+        if (v_only(fields[t], nx, nv, c[t], nz)) continue;
+        if (!x_allowed[t])
             return mg_fail(MG_EUNSUPPORTED, std::string("coefficient ") + names[t] +
-                                                " must be finite and depend on v only in this build");
+                                                " multiplies an x derivative and must be finite "
+                                                "and depend on v only in this build");
+        for (size_t k = 0; k < N; ++k)
+            if (!std::isfinite(fields[t][k]))
+                return mg_fail(MG_EINVAL, std::string("coefficient ") + names[t] + " is not finite");
+        std::vector<std::vector<double>> bs, as;
+        if (!low_rank(fields[t], nx, nv, MG_MAX_XDIAG, bs, as))
+            return mg_fail(MG_EUNSUPPORTED, std::string("coefficient ") + names[t] +
+                                                " is not a sum of at most 4 products b(v) a(x)");
+        c[t].assign(nv, 0.0);
+        for (size_t r = 0; r < bs.size(); ++r) {
+            const std::vector<double>& a = as[r];
+            bool constant = std::all_of(a.begin(), a.end(), [&](double v) { return v == a[0]; });
+            if (constant) {
+                for (int j = 0; j < nv; ++j) c[t][j] += bs[r][j] * a[0];
+            } else {
+                xb[t].push_back(bs[r]);
+                xid[t].push_back(xr.find_or_add(a));
+            }
+        }
+    }
     const double dx = (g->bx - g->ax) / (nx + 1), dv = (g->bv - g->av) / (nv + 1);
     Band Dv = first_difference(nv, dv), Dvv = second_difference(nv, dv);
 
-    // B = V_0 (x) I + V_1 (x) D^x
+    // B = V_0 (x) I + V_1 (x) D^x + sum W (x) diag(a)
     KOp B(nv), A(nv);
-    B.V[0] = band_axpby(1.0, band_diag(c[0]), 1.0, band_mul(band_diag(c[2]), Dv));
-    B.V[0] = band_axpby(1.0, B.V[0], 0.5, band_mul(band_diag(c[4]), Dvv));
-    B.V[1] = band_axpby(1.0, band_diag(c[1]), 1.0, band_mul(band_diag(c[3]), Dv));
-    // A = V_0 (x) I
-    A.V[0] = band_axpby(1.0, band_diag(c[5]), 1.0, band_mul(band_diag(c[6]), Dv));
-
-    KOp M[MG_NBASIS] = {B, A, KOp(nv), KOp(nv), KOp(nv), KOp(nv)};
-    bool ok = kop_mul(A, A, M[2]) && kop_comm(B, A, M[3]) && kop_comm(M[3], A, M[4]) &&
-              kop_comm(M[3], B, M[5]);
-    if (!ok) return mg_fail(MG_EUNSUPPORTED, "x-derivative power above 2 in the Magnus basis");
+    B.V[0] = band_axpby(1.0, band_diag(c[H]), 1.0, band_mul(band_diag(c[FV]), Dv));
+    B.V[0] = band_axpby(1.0, B.V[0], 0.5, band_mul(band_diag(c[GVV]), Dvv));
+    B.V[1] = band_axpby(1.0, band_diag(c[FX]), 1.0, band_mul(band_diag(c[GXV]), Dv));
+    for (size_t r = 0; r < xb[H].size(); ++r) B.add_w(xid[H][r], band_diag(xb[H][r]));
+    for (size_t r = 0; r < xb[FV].size(); ++r) B.add_w(xid[FV][r], band_mul(band_diag(xb[FV][r]), Dv));
+    for (size_t r = 0; r < xb[GVV].size(); ++r)
+        B.add_w(xid[GVV][r], band_axpby(0.5, band_mul(band_diag(xb[GVV][r]), Dvv), 0.0, Dvv));
+    // A = V_0 (x) I + sum W (x) diag(a)
+    A.V[0] = band_axpby(1.0, band_diag(c[SIG]), 1.0, band_mul(band_diag(c[SV]), Dv));
+    for (size_t r = 0; r < xb[SIG].size(); ++r) A.add_w(xid[SIG][r], band_diag(xb[SIG][r]));
+    for (size_t r = 0; r < xb[SV].size(); ++r) A.add_w(xid[SV][r], band_mul(band_diag(xb[SV][r]), Dv));
 
     const int nact = order == 1 ? 2 : (order == 2 ? 4 : 6);
+    KOp M[MG_NBASIS] = {B, A, KOp(nv), KOp(nv), KOp(nv), KOp(nv)};
+    std::string why;
+    bool ok = true;
+    // only the matrices the order uses have to exist in this form
+    if (nact > 2) ok = ok && kop_mul(A, A, xr, M[2], why) && kop_comm(B, A, xr, M[3], why);
+    if (nact > 4) ok = ok && kop_comm(M[3], A, xr, M[4], why) && kop_comm(M[3], B, xr, M[5], why);
+    if (!ok) return mg_fail(MG_EUNSUPPORTED, why);
+
     // Band radii actually used, after dropping cancellation residues.  A
-    // factor V_q multiplies (D^x)^q, whose norm is about (1/dx)^q, so entries
-    // are compared with the whole matrix through the weight (1/dx)^q: entries
-    // below 1e-14 of the largest weighted entry of the same basis matrix are
-    // zero in exact arithmetic and stem from rounding in the products (a
-    // factor can consist of residues only, e.g. the D^x part of [[B,A],B] for
-    // the constant-coefficient operator).
-    int R[3] = {0, 0, 0};
+    // factor V_q multiplies (D^x)^q, whose norm is about (1/dx)^q, and a factor
+    // W multiplies diag(a), whose norm is max|a|, so entries are compared with
+    // the whole matrix through these weights: entries below 1e-14 of the
+    // largest weighted entry of the same basis matrix are zero in exact
+    // arithmetic and stem from rounding in the products (a factor can consist
+    // of residues only, e.g. the D^x part of [[B,A],B] for the
+    // constant-coefficient operator).
+    int R[3] = {0, 0, 0}, RW = 0;
     const double wq[3] = {1.0, 1.0 / dx, 1.0 / (dx * dx)};
+    std::vector<double> wa(xr.vecs.size());
+    for (size_t k = 0; k < xr.vecs.size(); ++k) {
+        double m = 0.0;
+        for (double v : xr.vecs[k]) m = std::max(m, std::fabs(v));
+        wa[k] = m;
+    }
+    std::vector<int> used(xr.vecs.size(), 0);
     for (int l = 0; l < MG_NBASIS; ++l) {
         double mx = 0.0;
         for (int q = 0; q < 3; ++q)
             for (double v : M[l].V[q].a) mx = std::max(mx, std::fabs(v) * wq[q]);
+        for (size_t k = 0; k < M[l].W.size(); ++k)
+            for (double v : M[l].W[k].a) mx = std::max(mx, std::fabs(v) * wa[M[l].id[k]]);
         for (int q = 0; q < 3; ++q) {
             Band& V = M[l].V[q];
             for (double& v : V.a)
@@ -192,7 +351,28 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
                 for (int o = -V.r; o <= V.r; ++o)
                     if (V.get(i, i + o) != 0.0) R[q] = std::max(R[q], std::abs(o));
         }
+        for (size_t k = 0; k < M[l].W.size(); ++k) {
+            Band& W = M[l].W[k];
+            for (double& v : W.a)
+                if (std::fabs(v) * wa[M[l].id[k]] <= 1e-14 * mx) v = 0.0;
+            if (l >= nact) continue;
+            for (int i = 0; i < nv; ++i)
+                for (int o = -W.r; o <= W.r; ++o)
+                    if (W.get(i, i + o) != 0.0) {
+                        RW = std::max(RW, std::abs(o));
+                        used[M[l].id[k]] = 1;
+                    }
+        }
     }
+    // diagonal x-factors in use, numbered 0 .. nd-1 in registry order
+    std::vector<int> slot(xr.vecs.size(), -1);
+    int nd = 0;
+    for (size_t k = 0; k < xr.vecs.size(); ++k)
+        if (used[k]) slot[k] = nd++;
+    if (nd > MG_MAX_XDIAG)
+        return mg_fail(MG_EUNSUPPORTED, "more than 4 x-dependent factors in the Magnus basis");
+    if (RW > MG_XDIAG_RADIUS)
+        return mg_fail(MG_EUNSUPPORTED, "band radius of an x-dependent factor above 2");
     // highest power of D^x with a non-zero factor among the active matrices
     int qmax = 0;
     for (int l = 0; l < nact; ++l)
@@ -208,6 +388,9 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             qmax <= kShapes[k][3])
             shape = k;
     if (shape < 0) return mg_fail(MG_EUNSUPPORTED, "Magnus basis band radius above 3");
+    if (nd > 0 && shape > 1)
+        return mg_fail(MG_EUNSUPPORTED,
+                       "x-dependent coefficients are built for band shapes up to (2,1,0) in this build");
     for (int q = 0; q < 3; ++q) R[q] = kShapes[shape][q];
     ops->qmax = kShapes[shape][3];
 
@@ -215,8 +398,28 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     ops->order = order;
     ops->nactive = nact;
     for (int q = 0; q < 3; ++q) ops->R[q] = R[q];
-    ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (2 * R[2] + 1);
+    // x-dependent factors: the kernels take a fixed count (unused ones are zero)
+    ops->ND = nd > 0 ? MG_MAX_XDIAG : 0;
+    ops->RW = nd > 0 ? MG_XDIAG_RADIUS : 0;
+    ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (2 * R[2] + 1) + ops->ND * (2 * ops->RW + 1);
     ops->NBP = (ops->NB + 1) & ~1;
+    ops->xdiag_host.assign((size_t)ops->ND * nx, 0.0);
+    ops->xstat_host.assign((size_t)ops->ND * 4, 0.0);
+    for (size_t k = 0; k < xr.vecs.size(); ++k) {
+        if (slot[k] < 0) continue;
+        const std::vector<double>& a = xr.vecs[k];
+        double sum = 0.0, lo = a[0], hi = a[0];
+        for (int i = 0; i < nx; ++i) {
+            ops->xdiag_host[(size_t)slot[k] * nx + i] = a[i];
+            sum += a[i];
+            lo = std::min(lo, a[i]);
+            hi = std::max(hi, a[i]);
+        }
+        double* st = ops->xstat_host.data() + (size_t)slot[k] * 4;
+        st[0] = sum;                 // for the trace
+        st[1] = 0.5 * (hi + lo);     // midpoint and half-width of the values,
+        st[2] = 0.5 * (hi - lo);     // for the 1-norm bound
+    }
     // table rows are padded to the rows the kernel shape covers
     int rows = resident_rows(nx, nv);
     if (rows == 0) {
@@ -233,6 +436,12 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             for (int q = 0; q < 3; ++q) {
                 for (int o = -R[q]; o <= R[q]; ++o) row[off + o + R[q]] = M[l].V[q].get(j, j + o) * fold[q];
                 off += 2 * R[q] + 1;
+            }
+            for (size_t k = 0; k < M[l].W.size(); ++k) {
+                const int sl = slot[M[l].id[k]];
+                if (sl < 0) continue;
+                double* w = row + off + sl * (2 * ops->RW + 1);
+                for (int o = -ops->RW; o <= ops->RW; ++o) w[o + ops->RW] = M[l].W[k].get(j, j + o);
             }
         }
     return MG_OK;

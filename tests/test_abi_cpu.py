@@ -82,3 +82,36 @@ def test_error_vs_exact_argument_checks(lib):
     ex = mg.mg_exact(1.0, 0.5, 0.25, 1.0)
     assert lib.mg_error_vs_exact(ctypes.byref(g), ctypes.byref(ex), vp(8), vp(8), None, 1, 4,
                                  vp(8), None) == mg.MG_EINVAL      # 8 >> 4 == 0: empty window
+
+
+def _build_status(coeffs, n, order, lo=-5.0, hi=5.0):
+    """Status of mg_build_operators; combinations the factored form cannot hold
+    fail in the host build, before any device call, so this runs on the CPU."""
+    import workloads as wl
+    arrays = wl.sample_coefficients(coeffs, n, n, lo, hi, lo, hi)
+    try:
+        mg.build_operators(n, n, lo, hi, lo, hi, arrays, order)
+    except mg.MagnusError as e:
+        return e.code
+    return mg.MG_OK
+
+
+def test_unsupported_coefficient_combinations_are_reported():
+    import numpy as np
+    import workloads as wl
+    # x-dependent diffusion with the x transport at order 3: [[B,A],B] pairs
+    # a power of D^x with an x-dependent factor
+    assert _build_status(wl.langevin_variable_sigma_beta(), 16, 3) == mg.MG_EUNSUPPORTED
+    # the paper's variable set: x-dependent noise through d/dv meets D^x in [B,A]
+    assert _build_status(wl.langevin_paper_variable(1.1, 0.3), 16, 2) == mg.MG_EUNSUPPORTED
+    # x-dependent coefficient of an x derivative
+    assert _build_status(wl.Coefficients(fx=lambda x, v: -v * (1 + 0.1 * x)), 16, 2) == mg.MG_EUNSUPPORTED
+    # g^xx is outside this build
+    assert _build_status(wl.Coefficients(gxx=lambda x, v: 1.0 + 0 * x), 16, 2) == mg.MG_EUNSUPPORTED
+    # a coefficient grid of full rank is not a short sum of products b(v) a(x)
+    rng = np.random.default_rng(0)
+    noise = rng.random((16, 16))
+    assert _build_status(wl.Coefficients(gvv=lambda x, v: 1.0 + 0.1 * noise), 16, 2) == mg.MG_EUNSUPPORTED
+    # non-finite coefficients
+    assert _build_status(wl.Coefficients(gvv=lambda x, v: np.where(x > 0, np.nan, 1.0)), 16, 2) in (
+        mg.MG_EINVAL, mg.MG_EUNSUPPORTED)
