@@ -89,8 +89,9 @@ def _oracle_worker(args):
     errs = []
     for p in range(count):
         uT = magnus.iterated_magnus(basis, coef[p], u0)
-        uex = exact.solution_on_grid(g, w.T, w.a, w.sigma, w.s0sq, ps[p, 0], ps[p, 1])
-        errs.append(errors.relative_error(uex.reshape(w.n, w.n), uT.reshape(w.n, w.n)))
+        if not w.variable:       # no closed form: the oracle times the Magnus path only
+            uex = exact.solution_on_grid(g, w.T, w.a, w.sigma, w.s0sq, ps[p, 0], ps[p, 1])
+            errs.append(errors.relative_error(uex.reshape(w.n, w.n), uT.reshape(w.n, w.n)))
     return time.perf_counter() - t0, errs
 
 
@@ -109,12 +110,15 @@ def cpu_baseline(name: str):
         res = pool.map(_oracle_worker, jobs)
     wall = time.perf_counter() - t0
     npaths = cores * per
+    import workloads as wl
+    what = "integrals + Magnus" + ("" if wl.WORKLOADS[name].variable else " + error")
     return {"value": npaths / wall, "unit": "paths/s", "cores": cores, "kind": "oracle",
             "sample": f"{npaths} paths of the benchmark workload (paths 0..{npaths - 1}), "
-                      f"{per} per process, integrals + Magnus + error, wall {wall:.1f} s "
+                      f"{per} per process, {what}, wall {wall:.1f} s "
                       f"including operator build",
             "cpu_seconds": float(sum(r[0] for r in res)),
-            "mean_err": float(np.mean([e for r in res for e in r[1]]))}
+            "mean_err": (float(np.mean([e for r in res for e in r[1]]))
+                         if any(r[1] for r in res) else None)}
 
 
 # ---------------------------------------------------------------- GPU
@@ -158,12 +162,31 @@ def main():
     err = torch.empty(P, dtype=torch.float64, device=dev)
     ws = torch.empty(mg.workspace_bytes(ops, P, K), dtype=torch.uint8, device=dev)
     stats = torch.zeros((P, K, 2), dtype=torch.int32, device=dev)
+    uref = None
+    if w.variable:
+        # no closed form: the reference is Euler-Maruyama on the fine path
+        # itself (Nf steps, finer than every Euler run compared below), formed
+        # once before timing like the closed form is
+        log(f"fine Euler reference: {w.Nf} steps on {P} paths ...")
+        uref = u0.repeat(P, 1).contiguous()
+        flr = mg.euler_step(ops, uref, dW, w.T / w.Nf)
+        torch.cuda.synchronize()
+        if int((flr != 0).sum()):
+            raise RuntimeError("the fine Euler reference is not finite")
+
+    def error_of(u, rows=None, out=None):
+        """Per-path error against the closed form, or the fine reference."""
+        if uref is None:
+            pst = ps if rows is None else ps[:rows].contiguous()
+            return mg.error_vs_exact(ops, u, pathstat=pst, a=w.a, sigma=w.sigma, s0sq=w.s0sq,
+                                     T=w.T, err=out)
+        return mg.error_vs_exact(ops, u, uref=uref if rows is None else uref[:rows], err=out)
 
     def step(precision, with_stats=False):
         mg.iterated_integrals(dW, w.T, K, w.order, coef=coef, pathstat=ps)
         _, flags, st = mg.magnus_expmv(ops, coef, u0, precision=precision, uT=uT, ws=ws,
                                        want_stats=with_stats)
-        mg.error_vs_exact(ops, uT, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T, err=err)
+        error_of(uT, out=err)
         return flags, st
 
     if args.copy_calibration:
@@ -258,8 +281,7 @@ def main():
             dWE = mg.euler_increments(dW[:sub].contiguous(), NE)
             u = u0.repeat(sub, 1).contiguous()
             fl = mg.euler_step(ops, u, dWE, w.T / NE)
-            e = mg.error_vs_exact(ops, u, pathstat=ps[:sub].contiguous(), a=w.a, sigma=w.sigma,
-                                  s0sq=w.s0sq, T=w.T)
+            e = error_of(u, rows=sub)
             torch.cuda.synchronize()
             me = float(e.mean()) if int((fl != 0).sum()) == 0 else float("inf")
             log(f"euler NE=2^{q}: mean Err {me:.4e} (target {target:.4e})")
@@ -281,8 +303,7 @@ def main():
             u.copy_(u0.expand(P, N))
             mg.euler_increments(dW, NE, dWE=dWE_full)
             mg.euler_step(ops, u, dWE_full, w.T / NE)
-            mg.error_vs_exact(ops, u, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T,
-                              err=err)
+            error_of(u, out=err)
         e1.record()
         torch.cuda.synchronize()
         eu_ms = e0.elapsed_time(e1) / reps
@@ -330,7 +351,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "grid": [w.n, w.n], "domain": [w.lo, w.hi],
                    "paths": P, "magnus_steps": K, "order": w.order, "fine_increments": w.Nf,
-                   "T": w.T, "coefficients": {"fx": "-v", "gvv": w.a, "sv": w.sigma},
+                   "T": w.T,
+                   "coefficients": ({"fx": "-v", "gvv": "(1 + 0.3 sin(pi x/5) exp(-v^2/8))^2",
+                                     "sv": "0.5 + 0.2 tanh(v)"} if w.variable
+                                    else {"fx": "-v", "gvv": w.a, "sv": w.sigma}),
+                   "error_reference": (f"Euler-Maruyama, {w.Nf} steps" if w.variable
+                                       else "closed form"),
                    "initial": f"N(0,{w.s0sq} I)", "precision": "fp64",
                    "parallelism": "paths across workgroups, one GPU"},
         "mean_err_vs_exact": mean_err,

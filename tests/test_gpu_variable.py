@@ -105,3 +105,22 @@ def test_variable_above_128_is_reported_unsupported():
     with pytest.raises(mg.MagnusError) as ei:
         mg.magnus_expmv(ops, coef, u0, ws=torch.empty(1 << 20, dtype=torch.uint8, device=DEV))
     assert ei.value.code == mg.MG_EUNSUPPORTED
+
+
+def test_full_size_var128_sampled_paths():
+    """The variable-coefficient workload on 128x128 (512 paths, m2, 64 steps,
+    2^18 increments) in the launch configuration the benchmark times; paths
+    0, 311 and 511 are checked against the oracle one by one."""
+    w = wl.WORKLOADS["var-128-p512-m2-k64"]
+    say(f"variable magnus full {w.name}")
+    g, B, A, basis, ops = setup_problem(w.n, w.n, w.lo, w.hi, w.coefficients(), w.order)
+    dW = wl.brownian_increments(w.seed, w.paths, w.Nf)
+    u0 = wl.gaussian_density(w.n, w.n, w.lo, w.hi, w.lo, w.hi, w.s0sq).reshape(-1)
+    coef, _ = mg.iterated_integrals(to_dev(dW), w.T, w.K, w.order)
+    uT, flags, _ = mg.magnus_expmv(ops, coef, to_dev(u0))
+    torch.cuda.synchronize()
+    assert int(flags.abs().sum()) == 0
+    for p in (0, 311, 511):
+        c = integrals.path_coefficients(dW[p:p + 1], w.T, w.K, w.order)[0]
+        want = magnus.iterated_magnus(basis, c, u0)
+        assert rel(uT[p].cpu().numpy(), want) <= 1e-10, p

@@ -124,6 +124,10 @@ WORKLOADS: Dict[str, Workload] = {
                                               32, 3, 2 ** 14, 3, precision="fp32c"),
     "var-512-p512-m2-k64": Workload("var-512-p512-m2-k64", 512, -5.0, 5.0, 512, 64, 2, 2 ** 18, 4,
                                      variable=True, euler_steps=2 ** 14),
+    # the variable-coefficient workload on a 128^2 grid (the x-dependent
+    # operator runs on one workgroup per path up to 128 points per axis)
+    "var-128-p512-m2-k64": Workload("var-128-p512-m2-k64", 128, -5.0, 5.0, 512, 64, 2, 2 ** 18, 4,
+                                     variable=True, euler_steps=2 ** 14),
     "mixed-64-256-1024-m2-fp32c": Workload("mixed-64-256-1024-m2-fp32c", 64, -5.0, 5.0, 2048, 16, 2,
                                             2 ** 14, 5, precision="fp32c",
                                             extra=((64, 2048, 16, 5), (256, 512, 32, 6),
