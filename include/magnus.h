@@ -69,11 +69,14 @@ typedef struct {
 } mg_grid;
 
 /* Coefficient grids of eq. (generalSPDE), host arrays of nx*nv doubles in
- * [nv][nx] order; NULL means identically zero.  This build supports
- * coefficients that depend on v only (constant along x) for h, fx, fv, gxv,
- * gvv, sig, sv, with gxx = sx = 0: the constant- and v-dependent stochastic
- * Langevin SPDE (eq. (coeffsLangevinConst)).  Anything else returns
- * MG_EUNSUPPORTED. */
+ * [nv][nx] order; NULL means identically zero.  This build supports gxx = sx
+ * = 0; fx and gxv (the coefficients of x derivatives) depending on v only;
+ * h, fv, gvv, sig, sv depending on v, or on x and v when the grid is a sum of
+ * at most 4 products b(v) a(x) (to rounding) and no x derivative meets an
+ * x-dependent factor in the Magnus basis of the requested order.  That covers
+ * the constant- and v-dependent stochastic Langevin SPDE
+ * (eq. (coeffsLangevinConst)) at every order and an x,v-dependent diffusion
+ * g^vv at orders 1 and 2.  Anything else returns MG_EUNSUPPORTED. */
 typedef struct {
     const double *h, *fx, *fv, *gxx, *gxv, *gvv, *sig, *sx, *sv;
 } mg_coeffs;
@@ -94,8 +97,10 @@ typedef struct mg_ops mg_ops;
  * Builds on the host, in FP64, the drift B and noise A of eq. (SPDEvec) and
  * the commutators needed by Magnus order `order` (1..3) as exact products of
  * the truncated matrices, in the factored form
- *     M_l = sum_{q=0..2} V_{l,q} (x) (D^x)^q,  V_{l,q} banded nv x nv,
- * and uploads the tables to the current HIP device.
+ *     M_l = sum_{q=0..2} V_{l,q} (x) (D^x)^q + sum_t W_{l,t} (x) diag(a_t),
+ * V_{l,q}, W_{l,t} banded nv x nv, a_t the x profiles of the x-dependent
+ * coefficients, and uploads the tables to the current HIP device.  Operators
+ * with x-dependent factors run on grids up to 128 x 128.
  *   grid, coeffs : host, read during the call only.
  *   out          : receives a library-owned handle; free with
  *                  mg_free_operators.  The handle is immutable after build and
@@ -159,6 +164,42 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
                           const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
                           double tol, void* ws, size_t ws_bytes, int32_t* stats, int32_t* flags,
                           void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_magnus_expmv_multi  (the operation of mg_magnus_expmv for several
+ *                         independent batches in one call, e.g. groups of
+ *                         paths on grids of different sizes)
+ *
+ * Job i is the mg_magnus_expmv call with the fields of jobs[i] (same meaning,
+ * layouts and device pointers) and its own slice of one workspace: the
+ * slices follow each other in job order, each rounded up to 256 bytes.
+ * Every job is checked before anything is launched: an invalid job fails the
+ * whole call (mg_last_error names the job) and no kernel runs.  The jobs then
+ * run in order on `stream`.
+ *   jobs : host array of njobs descriptors;  ws : device workspace of
+ *          ws_bytes >= mg_workspace_bytes_multi(jobs, njobs).
+ * Errors: those of mg_magnus_expmv; MG_EINVAL (njobs < 0, NULL jobs).
+ * njobs = 0 is a no-op.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    const mg_ops* ops;
+    const double* coef;       /* device [P][K][6] */
+    int64_t P;
+    int32_t K;
+    const double* u0;         /* device FP64 [N] or [P][N] */
+    int32_t u0_broadcast;
+    double* uT;               /* device FP64 [P][N] */
+    int32_t precision;        /* MG_FP64 or MG_FP32C */
+    double tol;               /* <= 0: default of the precision */
+    int32_t* stats;           /* device [P][K][2] or NULL */
+    int32_t* flags;           /* device [P] or NULL */
+} mg_job;
+
+/* Total workspace of mg_magnus_expmv_multi (0 for an invalid job list). */
+size_t mg_workspace_bytes_multi(const mg_job* jobs, int32_t njobs);
+
+mg_status mg_magnus_expmv_multi(const mg_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                                void* stream);
 
 /* --------------------------------------------------------------------------
  * mg_euler_increments  (eq. (EulerMaruyama): Delta W_{t_k} = W_{t_{k+1}} - W_{t_k})

@@ -23,7 +23,8 @@ MG_FP64, MG_FP32C = 0, 1
 PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
-           "mg_workspace_bytes", "mg_magnus_expmv", "mg_euler_increments", "mg_euler_step",
+           "mg_workspace_bytes", "mg_magnus_expmv", "mg_workspace_bytes_multi",
+           "mg_magnus_expmv_multi", "mg_euler_increments", "mg_euler_step",
            "mg_error_vs_exact",
            "mg_last_error", "mg_timing_enable", "mg_timing_read", "mg_timing_reset", "mg_version")
 
@@ -42,6 +43,13 @@ class mg_grid(ctypes.Structure):
 class mg_coeffs(ctypes.Structure):
     _fields_ = [(n, ctypes.POINTER(ctypes.c_double))
                 for n in ("h", "fx", "fv", "gxx", "gxv", "gvv", "sig", "sx", "sv")]
+
+
+class mg_job(ctypes.Structure):
+    _fields_ = [("ops", ctypes.c_void_p), ("coef", ctypes.c_void_p), ("P", ctypes.c_int64),
+                ("K", ctypes.c_int32), ("u0", ctypes.c_void_p), ("u0_broadcast", ctypes.c_int32),
+                ("uT", ctypes.c_void_p), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("stats", ctypes.c_void_p), ("flags", ctypes.c_void_p)]
 
 
 class mg_exact(ctypes.Structure):
@@ -68,6 +76,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_workspace_bytes.argtypes = [vp, i64, i32, i32]
     lib.mg_workspace_bytes.restype = sz
     lib.mg_magnus_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, vp, vp, vp]
+    lib.mg_workspace_bytes_multi.argtypes = [ctypes.POINTER(mg_job), i32]
+    lib.mg_workspace_bytes_multi.restype = sz
+    lib.mg_magnus_expmv_multi.argtypes = [ctypes.POINTER(mg_job), i32, vp, sz, vp]
     lib.mg_euler_step.argtypes = [vp, vp, i64, vp, i32, dbl, i32, vp, sz, vp, vp]
     lib.mg_euler_increments.argtypes = [vp, i64, i64, i32, vp, vp]
     lib.mg_error_vs_exact.argtypes = [ctypes.POINTER(mg_grid), ctypes.POINTER(mg_exact), vp, vp,
@@ -77,7 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_timing_enable.argtypes = [i32]
     lib.mg_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
-                 "mg_magnus_expmv", "mg_euler_increments", "mg_euler_step", "mg_error_vs_exact", "mg_timing_enable",
+                 "mg_magnus_expmv", "mg_magnus_expmv_multi", "mg_euler_increments",
+                 "mg_euler_step", "mg_error_vs_exact", "mg_timing_enable",
                  "mg_timing_read", "mg_timing_reset"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -195,6 +207,52 @@ def magnus_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float =
         ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
         float(tol), _ptr(ws), ws.numel(), _ptr(stats), _ptr(flags), _stream(stream)))
     return uT, flags, stats
+
+
+def _addr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _job_array(jobs):
+    arr = (mg_job * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        arr[i] = mg_job(j["ops"].handle.value, _addr(j["coef"]), j["P"], j["K"], _addr(j["u0"]),
+                        j["u0_broadcast"], _addr(j["uT"]), PRECISIONS[j.get("precision", "fp64")],
+                        float(j.get("tol", 0.0)), _addr(j.get("stats")), _addr(j.get("flags")))
+    return arr
+
+
+def magnus_expmv_multi(jobs, ws=None, stream=None):
+    """mg_magnus_expmv_multi.  Each job is a dict with ops, coef [P][K][6], u0
+    ([N] or [P][N]), and optionally precision, tol, uT, want_stats; returns a
+    list of (uT, flags, stats) in job order."""
+    import torch
+    prepared = []
+    for j in jobs:
+        _dev_f64(j["coef"], "coef")
+        _dev_f64(j["u0"], "u0")
+        P, K, _ = j["coef"].shape
+        N = j["ops"].grid.nx * j["ops"].grid.nv
+        bcast = 1 if j["u0"].dim() == 1 else 0
+        if j["u0"].numel() != (N if bcast else P * N):
+            raise ValueError("u0 has the wrong size")
+        dev = j["coef"].device
+        uT = j.get("uT")
+        if uT is None:
+            uT = torch.empty((P, N), dtype=torch.float64, device=dev)
+        flags = torch.zeros(P, dtype=torch.int32, device=dev)
+        stats = torch.zeros((P, K, 2), dtype=torch.int32, device=dev) if j.get("want_stats") else None
+        prepared.append({"ops": j["ops"], "coef": j["coef"], "P": P, "K": K, "u0": j["u0"],
+                         "u0_broadcast": bcast, "uT": uT, "precision": j.get("precision", "fp64"),
+                         "tol": j.get("tol", 0.0), "stats": stats, "flags": flags})
+    arr = _job_array(prepared)
+    lib = load_library()
+    need = int(lib.mg_workspace_bytes_multi(arr, len(prepared)))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8,
+                         device=prepared[0]["coef"].device if prepared else "cuda")
+    _check(lib.mg_magnus_expmv_multi(arr, len(prepared), _ptr(ws), ws.numel(), _stream(stream)))
+    return [(j["uT"], j["flags"], j["stats"]) for j in prepared]
 
 
 def euler_increments(dW, NE: int, dWE=None, stream=None):

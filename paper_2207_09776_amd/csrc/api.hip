@@ -176,53 +176,140 @@ size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t preci
     return bytes;
 }
 
+namespace {
+
+// A validated mg_magnus_expmv call: everything checked, nothing launched.
+struct ExpmvCall {
+    const mg_ops* ops;
+    const double* coef;
+    int64_t P;
+    int K;
+    const double* u0;
+    int bcast;
+    double* uT;
+    int precision;
+    double tol;
+    int32_t* stats;
+    int32_t* flags;
+    Family fam = Family::None;
+    CoopPlan plan;
+    size_t tbytes = 0, need = 0;
+};
+
+// Checks one call (everything but the workspace, which the callers check);
+// `where` prefixes the error message.
+mg_status expmv_prepare(ExpmvCall& c, const std::string& where) {
+    if (!c.ops) return mg_fail(MG_EINVAL, where + ": NULL ops");
+    if (c.P < 0 || c.K < 1) return mg_fail(MG_ESHAPE, where + ": need P >= 0 and K >= 1");
+    if (c.P > 0x7fffffff / (int64_t)c.K) return mg_fail(MG_ESHAPE, where + ": P*K too large");
+    if (c.precision != MG_FP64 && c.precision != MG_FP32C)
+        return mg_fail(MG_EINVAL, where + ": unknown precision");
+    if (!(c.tol == c.tol) || c.tol >= 1.0) return mg_fail(MG_EINVAL, where + ": tol must be < 1");
+    if (c.tol <= 0.0) c.tol = c.precision == MG_FP64 ? 0x1p-53 : 0x1p-24;
+    c.fam = family_of(c.ops, c.precision);
+    if (c.fam == Family::None)
+        return mg_fail(MG_EUNSUPPORTED,
+                       where + (c.ops->ND > 0 ? ": x-dependent coefficients need nx, nv <= 128"
+                                              : ": no kernel for this grid size"));
+    if (c.P == 0) return MG_OK;
+    if (!c.coef || !c.u0 || !c.uT) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (c.fam == Family::Coop) {
+        hipError_t e = coop_plan(c.ops, c.precision, c.P, &c.plan);
+        if (e != hipSuccess)
+            return mg_fail(MG_EUNSUPPORTED,
+                           where + ": no cooperative plan: " + hipGetErrorString(e) + " (stage " +
+                               std::to_string(c.plan.stage) + ", G " + std::to_string(c.plan.G) +
+                               ", per_cu " + std::to_string(c.plan.per_cu) + ", cus " +
+                               std::to_string(c.plan.cus) + ", lds " +
+                               std::to_string(c.plan.lds) + ")");
+    }
+    c.tbytes = mg_table_bytes(c.ops, c.precision);
+    c.need = (size_t)c.P * c.K * c.tbytes + (c.fam == Family::Coop ? c.plan.bytes : 0);
+    return MG_OK;
+}
+
+// Launches a prepared call with its workspace.
+mg_status expmv_launch(const ExpmvCall& c, char* ws, hipStream_t s, const std::string& where) {
+    if (c.P == 0) return MG_OK;
+    char* tables = ws;
+    hipError_t e = launch_assemble(c.ops, c.coef, c.P, c.K, c.tol, c.precision, tables, s);
+    if (e != hipSuccess) return hip_fail(e, (where + " (assemble)").c_str());
+    TimingScope ts("expmv", s);
+    if (c.fam == Family::Resident)
+        e = launch_expmv_resident(c.ops, tables, c.tbytes, c.P, c.K, c.u0, c.bcast, c.uT, c.tol,
+                                  c.precision, c.stats, c.flags, s, false);
+    else
+        e = launch_expmv_coop(c.ops, tables, c.tbytes, c.P, c.K, c.u0, c.bcast, c.uT, c.tol,
+                              c.precision, c.stats, c.flags, tables + (size_t)c.P * c.K * c.tbytes,
+                              c.plan, s);
+    ts.done();
+    return e == hipSuccess ? MG_OK : hip_fail(e, where.c_str());
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
 mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
                           const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
                           double tol, void* ws, size_t ws_bytes, int32_t* stats, int32_t* flags,
                           void* stream) {
     g_last_error.clear();
-    if (!ops) return mg_fail(MG_EINVAL, "mg_magnus_expmv: NULL ops");
-    if (P < 0 || K < 1) return mg_fail(MG_ESHAPE, "mg_magnus_expmv: need P >= 0 and K >= 1");
-    if (P > 0x7fffffff / (int64_t)K) return mg_fail(MG_ESHAPE, "mg_magnus_expmv: P*K too large");
-    if (precision != MG_FP64 && precision != MG_FP32C)
-        return mg_fail(MG_EINVAL, "mg_magnus_expmv: unknown precision");
-    if (!(tol == tol) || tol >= 1.0) return mg_fail(MG_EINVAL, "mg_magnus_expmv: tol must be < 1");
-    if (tol <= 0.0) tol = precision == MG_FP64 ? 0x1p-53 : 0x1p-24;
-    hipStream_t s = (hipStream_t)stream;
-    const Family fam = family_of(ops, precision);
-    if (fam == Family::None)
-        return mg_fail(MG_EUNSUPPORTED,
-                       ops->ND > 0 ? "mg_magnus_expmv: x-dependent coefficients need nx, nv <= 128"
-                                   : "mg_magnus_expmv: no kernel for this grid size");
-    if (P == 0) return MG_OK;
-    if (!coef || !u0 || !uT || !ws) return mg_fail(MG_EINVAL, "mg_magnus_expmv: NULL pointer");
-    CoopPlan plan;
-    if (fam == Family::Coop) {
-        hipError_t e = coop_plan(ops, precision, P, &plan);
-        if (e != hipSuccess)
-            return mg_fail(MG_EUNSUPPORTED,
-                           std::string("mg_magnus_expmv: no cooperative plan: ") +
-                               hipGetErrorString(e) + " (stage " + std::to_string(plan.stage) +
-                               ", G " + std::to_string(plan.G) + ", per_cu " +
-                               std::to_string(plan.per_cu) + ", cus " + std::to_string(plan.cus) +
-                               ", lds " + std::to_string(plan.lds) + ")");
+    ExpmvCall c{ops, coef, P, K, u0, u0_broadcast, uT, precision, tol, stats, flags};
+    const std::string where = "mg_magnus_expmv";
+    mg_status st = expmv_prepare(c, where);
+    if (st != MG_OK || P == 0) return st;
+    if (!ws) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (ws_bytes < c.need)
+        return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
+    return expmv_launch(c, (char*)ws, (hipStream_t)stream, where);
+}
+
+size_t mg_workspace_bytes_multi(const mg_job* jobs, int32_t njobs) {
+    if (!jobs || njobs <= 0) return 0;
+    size_t total = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const mg_job& j = jobs[i];
+        if (j.P <= 0) continue;
+        const size_t b = mg_workspace_bytes(j.ops, j.P, j.K, j.precision);
+        if (b == 0) return 0;
+        total += round256(b);
     }
-    const size_t tbytes = mg_table_bytes(ops, precision);
-    const size_t need = (size_t)P * K * tbytes + (fam == Family::Coop ? plan.bytes : 0);
-    if (ws_bytes < need)
-        return mg_fail(MG_ENOMEM, "mg_magnus_expmv: workspace smaller than mg_workspace_bytes()");
-    char* tables = (char*)ws;
-    hipError_t e = launch_assemble(ops, coef, P, K, tol, precision, tables, s);
-    if (e != hipSuccess) return hip_fail(e, "mg_magnus_expmv (assemble)");
-    TimingScope ts("expmv", s);
-    if (fam == Family::Resident)
-        e = launch_expmv_resident(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, tol, precision,
-                                  stats, flags, s, false);
-    else
-        e = launch_expmv_coop(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, tol, precision,
-                              stats, flags, tables + (size_t)P * K * tbytes, plan, s);
-    ts.done();
-    return e == hipSuccess ? MG_OK : hip_fail(e, "mg_magnus_expmv");
+    return total;
+}
+
+mg_status mg_magnus_expmv_multi(const mg_job* jobs, int32_t njobs, void* ws, size_t ws_bytes,
+                                void* stream) {
+    g_last_error.clear();
+    if (njobs < 0) return mg_fail(MG_EINVAL, "mg_magnus_expmv_multi: njobs < 0");
+    if (njobs == 0) return MG_OK;
+    if (!jobs) return mg_fail(MG_EINVAL, "mg_magnus_expmv_multi: NULL jobs");
+    std::vector<ExpmvCall> calls;
+    calls.reserve(njobs);
+    size_t total = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        const mg_job& j = jobs[i];
+        ExpmvCall c{j.ops, j.coef, j.P, j.K, j.u0, j.u0_broadcast, j.uT, j.precision, j.tol,
+                    j.stats, j.flags};
+        mg_status st = expmv_prepare(c, "mg_magnus_expmv_multi: job " + std::to_string(i));
+        if (st != MG_OK) return st;
+        if (c.P > 0) total += round256(c.need);
+        calls.push_back(c);
+    }
+    if (total > 0 && !ws) return mg_fail(MG_EINVAL, "mg_magnus_expmv_multi: NULL workspace");
+    if (ws_bytes < total)
+        return mg_fail(MG_ENOMEM,
+                       "mg_magnus_expmv_multi: workspace smaller than mg_workspace_bytes_multi()");
+    char* base = (char*)ws;
+    size_t off = 0;
+    for (int32_t i = 0; i < njobs; ++i) {
+        if (calls[i].P == 0) continue;
+        mg_status st = expmv_launch(calls[i], base + off, (hipStream_t)stream,
+                                    "mg_magnus_expmv_multi: job " + std::to_string(i));
+        if (st != MG_OK) return st;
+        off += round256(calls[i].need);
+    }
+    return MG_OK;
 }
 
 mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* dWE, int32_t NE,

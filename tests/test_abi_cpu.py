@@ -115,3 +115,17 @@ def test_unsupported_coefficient_combinations_are_reported():
     # non-finite coefficients
     assert _build_status(wl.Coefficients(gvv=lambda x, v: np.where(x > 0, np.nan, 1.0)), 16, 2) in (
         mg.MG_EINVAL, mg.MG_EUNSUPPORTED)
+
+
+def test_multi_job_argument_checks(lib):
+    """mg_magnus_expmv_multi checks every job before launching anything."""
+    lib.mg_magnus_expmv_multi.restype = ctypes.c_int32
+    assert lib.mg_magnus_expmv_multi(None, 0, None, 0, None) == mg.MG_OK
+    assert lib.mg_magnus_expmv_multi(None, -1, None, 0, None) == mg.MG_EINVAL
+    assert lib.mg_magnus_expmv_multi(None, 2, None, 0, None) == mg.MG_EINVAL
+    jobs = (mg.mg_job * 2)()
+    jobs[0] = mg.mg_job(None, None, 4, 4, None, 1, None, 0, 0.0, None, None)   # NULL ops
+    assert lib.mg_magnus_expmv_multi(jobs, 2, None, 0, None) == mg.MG_EINVAL
+    assert b"job 0" in lib.mg_last_error()
+    assert lib.mg_workspace_bytes_multi(None, 1) == 0
+    assert lib.mg_workspace_bytes_multi(jobs, 2) == 0

@@ -303,3 +303,53 @@ def test_full_size_256_fp32c_sampled_path():
     c = integrals.path_coefficients(dW[p:p + 1], w.T, w.K, w.order)[0]
     want = magnus.iterated_magnus(basis, c, u0)
     assert rel(uT[p].cpu().numpy(), want) <= 1e-5
+
+
+# ------------------------------------------------------------------ several batches in one call
+def test_multi_job_call_matches_single_calls_and_oracle():
+    """Three batches of different sizes and forms in one mg_magnus_expmv_multi
+    call: each equals its own mg_magnus_expmv call bitwise and the oracle
+    within the tolerance of its form."""
+    say("magnus multi-job")
+    specs = [  # (nx, nv, order, P, K, Nf, T, precision, tol)
+        (32, 32, 2, 2, 4, 256, 1.0, "fp64", 1e-10),
+        (64, 64, 3, 3, 8, 512, 1.0, "fp32c", 1e-5),
+        (200, 150, 2, 1, 2, 256, 0.25, "fp64", 1e-10),
+    ]
+    coeffs = wl.langevin_constant(1.0, 0.5)
+    jobs, refs = [], []
+    for i, (nx, nv, order, P, K, Nf, T, prec, tol) in enumerate(specs):
+        g, B, A, basis, ops = setup_problem(nx, nv, -5.0, 5.0, coeffs, order)
+        dW = wl.brownian_increments(40 + i, P, Nf, T=T)
+        u0 = wl.gaussian_density(nx, nv, -5, 5, -5, 5, 0.25).reshape(-1)
+        coef, _ = mg.iterated_integrals(to_dev(dW), T, K, order)
+        jobs.append({"ops": ops, "coef": coef, "u0": to_dev(u0), "precision": prec,
+                     "want_stats": True})
+        want = magnus.iterated_magnus_paths(basis, integrals.path_coefficients(dW, T, K, order), u0)
+        single, _, _ = mg.magnus_expmv(ops, coef, to_dev(u0), precision=prec)
+        refs.append((want, single, tol))
+    out = mg.magnus_expmv_multi(jobs)
+    torch.cuda.synchronize()
+    for (uT, flags, stats), (want, single, tol) in zip(out, refs):
+        assert int(flags.abs().sum()) == 0
+        assert torch.equal(uT, single)
+        for p in range(uT.shape[0]):
+            assert rel(uT[p].cpu().numpy(), want[p]) <= tol
+
+
+def test_multi_job_invalid_job_launches_nothing():
+    say("magnus multi-job invalid")
+    coeffs = wl.langevin_constant(1.0, 0.5)
+    g, B, A, basis, ops = setup_problem(24, 24, -5.0, 5.0, coeffs, 2)
+    dW = wl.brownian_increments(3, 2, 64)
+    coef, _ = mg.iterated_integrals(to_dev(dW), 1.0, 4, 2)
+    u0 = to_dev(wl.gaussian_density(24, 24, -5, 5, -5, 5, 0.25).reshape(-1))
+    sentinel = torch.full((2, 24 * 24), float("nan"), dtype=torch.float64, device=DEV)
+    bad = torch.zeros((2, 4, 6), dtype=torch.float64, device=DEV)
+    jobs = [{"ops": ops, "coef": coef, "u0": u0, "uT": sentinel},
+            {"ops": ops, "coef": bad, "u0": u0, "precision": "fp64", "tol": 2.0}]   # tol >= 1
+    with pytest.raises(mg.MagnusError) as ei:
+        mg.magnus_expmv_multi(jobs)
+    torch.cuda.synchronize()
+    assert ei.value.code == mg.MG_EINVAL and "job 1" in str(ei.value)
+    assert bool(torch.isnan(sentinel).all())
