@@ -122,6 +122,166 @@ def cpu_baseline(name: str):
 
 
 # ---------------------------------------------------------------- GPU
+FP32_VECTOR_PEAK = 157.3e12          # MI355X FP32 vector, FLOP/s
+
+
+def _mixed_oracle_worker(args):
+    """Child process: the oracle on paths of the smallest group of the mixed
+    workload (integrals + Magnus + error); returns seconds."""
+    n, K, seed, first, count, lo, hi, order, Nf, T, s0sq, a, sigma = args
+    os.environ["OMP_NUM_THREADS"] = "1"
+    import workloads as wl
+    from oracle import errors, exact, integrals, magnus, operators
+    t0 = time.perf_counter()
+    g = operators.Grid(n, n, lo, hi, lo, hi)
+    B, A = operators.drift_and_noise(g, wl.langevin_constant(a, sigma))
+    basis = operators.magnus_basis(B, A)
+    dW = wl.brownian_increments(seed, first + count, Nf, T, first=first, count=count)
+    u0 = wl.gaussian_density(n, n, lo, hi, lo, hi, s0sq).reshape(-1)
+    coef = integrals.path_coefficients(dW, T, K, order)
+    ps = integrals.path_statistics(dW, T)
+    errs = []
+    for p in range(count):
+        uT = magnus.iterated_magnus(basis, coef[p], u0)
+        uex = exact.solution_on_grid(g, T, a, sigma, s0sq, ps[p, 0], ps[p, 1])
+        errs.append(errors.relative_error(uex.reshape(n, n), uT.reshape(n, n)))
+    return time.perf_counter() - t0, errs
+
+
+def run_mixed(args, w):
+    """The mixed-size workload: groups of paths on grids of different sizes
+    (constant-coefficient Langevin, FP32C), all in one mg_magnus_expmv_multi
+    call per step; value = all paths of all groups per second."""
+    import torch
+    import paper_2207_09776_amd as mg
+    import workloads as wl
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    coeffs = w.coefficients()
+    groups = []
+    for (n, paths, K, seed) in w.extra:
+        N = n * n
+        ops = mg.build_operators(n, n, w.lo, w.hi, w.lo, w.hi,
+                                 wl.sample_coefficients(coeffs, n, n, w.lo, w.hi, w.lo, w.hi),
+                                 w.order)
+        dW = torch.from_numpy(wl.brownian_increments(seed, paths, w.Nf, w.T)).to(dev)
+        u0 = torch.from_numpy(wl.gaussian_density(n, n, w.lo, w.hi, w.lo, w.hi, w.s0sq)
+                              .reshape(-1)).to(dev)
+        groups.append({"n": n, "P": paths, "K": K, "seed": seed, "ops": ops, "dW": dW, "u0": u0,
+                       "coef": torch.empty((paths, K, 6), dtype=torch.float64, device=dev),
+                       "ps": torch.empty((paths, 2), dtype=torch.float64, device=dev),
+                       "uT": torch.empty((paths, N), dtype=torch.float64, device=dev),
+                       "err": torch.empty(paths, dtype=torch.float64, device=dev)})
+        log(f"group {n}^2: {paths} paths, K={K}, seed {seed}")
+    prec = w.precision
+    jobs = [{"ops": g["ops"], "coef": g["coef"], "u0": g["u0"], "uT": g["uT"], "precision": prec}
+            for g in groups]
+
+    def step(with_stats=False):
+        for g in groups:
+            mg.iterated_integrals(g["dW"], w.T, g["K"], w.order, coef=g["coef"], pathstat=g["ps"])
+        for j in jobs:
+            j["want_stats"] = with_stats
+        out = mg.magnus_expmv_multi(jobs, ws=ws)
+        for g in groups:
+            mg.error_vs_exact(g["ops"], g["uT"], pathstat=g["ps"], a=w.a, sigma=w.sigma,
+                              s0sq=w.s0sq, T=w.T, err=g["err"])
+        return out
+
+    total_ws = 0
+    for g in groups:
+        total_ws += (mg.workspace_bytes(g["ops"], g["P"], g["K"], prec) + 255) // 256 * 256
+    ws = torch.empty(total_ws, dtype=torch.uint8, device=dev)
+    out = step(with_stats=True)
+    for _ in range(max(0, args.warmup - 1)):
+        step()
+    torch.cuda.synchronize()
+    per_group = []
+    for g, (uT, fl, st) in zip(groups, out):
+        stn = st.cpu().numpy()
+        per_group.append({"grid": g["n"], "paths": g["P"], "magnus_steps": g["K"],
+                          "mean_err": float(g["err"].mean()), "flagged_paths": int((fl != 0).sum()),
+                          "terms_per_path": float(stn[..., 0].sum()) / g["P"],
+                          "terms": int(stn[..., 0].sum())})
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    total_paths = sum(g["P"] for g in groups)
+    # per-group Taylor kernel time: each group's call alone, timed by the library
+    for g, pg in zip(groups, per_group):
+        ws_g = torch.empty(mg.workspace_bytes(g["ops"], g["P"], g["K"], prec), dtype=torch.uint8,
+                           device=dev)
+        mg.magnus_expmv(g["ops"], g["coef"], g["u0"], precision=prec, uT=g["uT"], ws=ws_g)
+        torch.cuda.synchronize()
+        mg.timing_reset()
+        mg.timing_enable(True)
+        mg.magnus_expmv(g["ops"], g["coef"], g["u0"], precision=prec, uT=g["uT"], ws=ws_g)
+        torch.cuda.synchronize()
+        mg.timing_enable(False)
+        k_ms, k_n = mg.timing_read("expmv")
+        pg["launch_ms"] = k_ms / max(k_n, 1)
+        pg["achieved_TFLOPs"] = pg["terms"] * g["n"] ** 2 * (2 * NNZ_ROW[w.order] + 2) / (
+            pg["launch_ms"] / 1e3) / 1e12
+        log(f"group {g['n']}^2: Err {pg['mean_err']:.4e}, {pg['terms_per_path']:.0f} terms/path, "
+            f"Taylor kernel {pg['launch_ms']:.3f} ms")
+        del ws_g
+    dom = max(per_group, key=lambda pg: pg["launch_ms"])
+    peak = FP32_VECTOR_PEAK if prec == "fp32c" else FP64_VECTOR_PEAK
+    roofline = {"bound": "alu", "achieved": dom["achieved_TFLOPs"], "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": dom["achieved_TFLOPs"] * 1e12 / peak, "traffic": None,
+                "kernel": ("expmv_coop_kernel" if dom["grid"] > 128 else "expmv_resident_kernel")
+                          + f" ({dom['grid']}^2 group)",
+                "flops_per_point_term": 2 * NNZ_ROW[w.order] + 2, "launch_ms": dom["launch_ms"]}
+    cpu = None
+    if not args.no_cpu:
+        import multiprocessing as mpr
+        try:
+            cores = len(os.sched_getaffinity(0))
+        except AttributeError:
+            cores = os.cpu_count() or 1
+        cores = max(1, min(cores, 16))
+        n, paths, K, seed = w.extra[0]
+        per = 4
+        jobs_cpu = [(n, K, seed, i * per, per, w.lo, w.hi, w.order, w.Nf, w.T, w.s0sq, w.a, w.sigma)
+                    for i in range(cores)]
+        t0 = time.perf_counter()
+        with mpr.get_context("spawn").Pool(cores) as pool:
+            res = pool.map(_mixed_oracle_worker, jobs_cpu)
+        wall = time.perf_counter() - t0
+        cpu = {"value": cores * per / wall, "unit": "paths/s", "cores": cores, "kind": "oracle",
+               "sample": f"{cores * per} paths of the {n}^2 group only (the larger grids take "
+                         f"minutes per path on the host), {per} per process, integrals + Magnus "
+                         f"+ error, wall {wall:.1f} s",
+               "mean_err": float(np.mean([e for r in res for e in r[1]]))}
+    out = {
+        "metric": "paths/s at matched L2 error vs exact sol. (Magnus vs Euler, FP32 vs FP64); HBM GB/s",
+        "value": total_paths / (ms_per_step / 1e3),
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "groups": [[n, P, K] for (n, P, K, _) in w.extra],
+                   "domain": [w.lo, w.hi], "order": w.order, "fine_increments": w.Nf, "T": w.T,
+                   "coefficients": {"fx": "-v", "gvv": w.a, "sv": w.sigma},
+                   "initial": f"N(0,{w.s0sq} I)", "precision": prec,
+                   "parallelism": "one mg_magnus_expmv_multi call per step, one GPU"},
+        "groups": per_group,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +306,8 @@ def main():
     import workloads as wl
 
     w = wl.WORKLOADS[args.workload]
+    if w.extra:
+        return run_mixed(args, w)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"workload {w.name}: {w.n}^2, P={w.paths}, K={w.K}, order={w.order}, Nf={w.Nf}")

@@ -353,3 +353,42 @@ def test_multi_job_invalid_job_launches_nothing():
     torch.cuda.synchronize()
     assert ei.value.code == mg.MG_EINVAL and "job 1" in str(ei.value)
     assert bool(torch.isnan(sentinel).all())
+
+
+def test_full_size_mixed_groups():
+    """The mixed-size workload (64^2 x 2048, 256^2 x 512, 1024^2 x 64 paths,
+    FP32C) in one mg_magnus_expmv_multi call, as the benchmark runs it.
+    Sampled 64^2 paths against the oracle (1e-5); the larger grids, whose
+    paths the oracle cannot afford, through properties: finite results and a
+    median error against the closed form below a few times the second-order
+    discretisation error of the grid (the oracle gives 9.2e-4 at 256^2; scaled
+    by dx^2, 5.8e-5 at 1024^2), far below the O(1) error of a wrong operator
+    or sum.  (The median: single rough paths can have larger Magnus errors.)"""
+    w = wl.WORKLOADS["mixed-64-256-1024-m2-fp32c"]
+    say(f"magnus full {w.name}")
+    coeffs = w.coefficients()
+    jobs, groups = [], []
+    for (n, paths, K, seed) in w.extra:
+        g, B, A, basis, ops = setup_problem(n, n, w.lo, w.hi, coeffs, w.order)
+        dW = wl.brownian_increments(seed, paths, w.Nf)
+        u0 = wl.gaussian_density(n, n, w.lo, w.hi, w.lo, w.hi, w.s0sq).reshape(-1)
+        coef, ps = mg.iterated_integrals(to_dev(dW), w.T, K, w.order)
+        jobs.append({"ops": ops, "coef": coef, "u0": to_dev(u0), "precision": "fp32c"})
+        groups.append((n, K, dW, u0, basis, ops, ps))
+    out = mg.magnus_expmv_multi(jobs)
+    torch.cuda.synchronize()
+    bounds = {256: 2e-3, 1024: 2e-4}
+    for (n, K, dW, u0, basis, ops, ps), (uT, flags, _) in zip(groups, out):
+        assert int(flags.abs().sum()) == 0, n
+        assert bool(torch.isfinite(uT).all()), n
+        if n == 64:
+            for p in (0, 1000, 2047):
+                c = integrals.path_coefficients(dW[p:p + 1], w.T, K, w.order)[0]
+                want = magnus.iterated_magnus(basis, c, u0)
+                assert rel(uT[p].cpu().numpy(), want) <= 1e-5, p
+        else:
+            err = mg.error_vs_exact(ops, uT, pathstat=ps, a=w.a, sigma=w.sigma, s0sq=w.s0sq, T=w.T)
+            torch.cuda.synchronize()
+            med = float(err.median())
+            say(f"  {n}^2 median error vs closed form {med:.3e}, mean {float(err.mean()):.3e}")
+            assert med <= bounds[n], (n, med)
