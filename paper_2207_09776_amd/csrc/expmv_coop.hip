@@ -19,8 +19,15 @@
 //     halo rows.
 // Waiting is bounded: after kSpinLimit polls the launch is aborted through a
 // shared word, every workgroup leaves its loops and the paths get
-// MG_FLAG_ABORT.  The arithmetic per term is the one of the resident kernel
-// (FP64 unscaled chain, or the compensated FP32 chain).
+// MG_FLAG_ABORT.
+//
+// Every access to the exchange area (halo rows, norms, counters) is a
+// device-coherent (agent-scope) relaxed atomic, which neither hits a stale
+// L1 line nor leaves data in a non-coherent cache; a vmcnt(0) wait orders a
+// member's data stores before its counter store, and the readers load the
+// data after they have seen the counters.  No L2 write-back or invalidation is
+// issued, so the per-term synchronisation does not flush the caches that hold
+// the coefficient tables.
 
 #include <algorithm>
 #include <cmath>
@@ -53,6 +60,20 @@ struct CoopArgs {
     int ngroups;
     int xcd_map;       // members of a group on one XCD (blockIdx mod 8)
 };
+
+// Stores issued so far by this wave have completed (device-coherent stores
+// are then visible to every later device-coherent load).
+__device__ inline void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Device-coherent accesses to the exchange area.
+template <class T>
+__device__ inline T xload(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ inline void xstore(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 constexpr int kRHX = 3;   // halo rows reserved per side in the exchange area
 
@@ -152,7 +173,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
-                    if (i < nx) xh_row(g, par, 0, s)[i] = d[s][q];
+                    if (i < nx) xstore(xh_row(g, par, 0, s) + i, d[s][q]);
                 }
         }
         if (w == NW - 1 && g + 1 < G) {
@@ -161,10 +182,10 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
-                    if (i < nx) xh_row(g, par, 1, s)[i] = d[RJ - RH + s][q];
+                    if (i < nx) xstore(xh_row(g, par, 1, s) + i, d[RJ - RH + s][q]);
                 }
         }
-        if (w == 0 || w == NW - 1) __threadfence();
+        if (w == 0 || w == NW - 1) wait_stores();
     };
 
     // One group synchronisation; the caller has executed a barrier after its
@@ -175,33 +196,29 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
         if (w == 0) {
             if (lane == 0) {
                 double* x = xn_at(g, par);
-                x[0] = p0;
-                x[1] = p1;
-                x[2] = p2;
+                xstore(x, p0);
+                xstore(x + 1, p1);
+                xstore(x + 2, p2);
             }
-            __threadfence();
-            if (lane == 0)
-                __hip_atomic_store(my_cnt, counter + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            wait_stores();
+            if (lane == 0) xstore(my_cnt, counter + 1);
             // wait until every member published this sync (lane m watches member m)
             int spins = 0;
             bool ab = false;
             for (;;) {
                 bool ready = true;
                 for (int mm = lane; mm < G; mm += 64)
-                    if (__hip_atomic_load(grp_cnt + mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                        counter + 1)
-                        ready = false;
+                    if (xload(grp_cnt + mm) < counter + 1) ready = false;
                 if (__all(ready)) break;
-                if (++spins > kSpinLimit ||
-                    __hip_atomic_load(a.abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                if (++spins > kSpinLimit || xload(a.abort_word)) {
                     ab = true;
-                    if (lane == 0)
-                        __hip_atomic_store(a.abort_word, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (lane == 0) xstore(a.abort_word, 1);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            __threadfence();
+            // the data loads below stay after the counter loads
+            asm volatile("" ::: "memory");
             if (lane == 0) sh[0] = ab ? 1 : 0;
         }
         __syncthreads();
@@ -209,9 +226,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
         double o0 = 0.0, o1 = 0.0, o2 = 0.0;
         for (int mm = lane; mm < G; mm += 64) {
             const double* x = xn_at(mm, par);
-            o0 = fmax(o0, x[0]);
-            o1 = fmax(o1, x[1]);
-            o2 = fmax(o2, x[2]);
+            o0 = fmax(o0, xload(x));
+            o1 = fmax(o1, xload(x + 1));
+            o2 = fmax(o2, xload(x + 2));
         }
         for (int o = 32; o > 0; o >>= 1) {
             o0 = fmax(o0, __shfl_xor(o0, o, 64));
@@ -301,7 +318,12 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
 #pragma unroll
                             for (int q = 0; q < PX; ++q) {
                                 const int i = lane * PX + q;
-                                top[s2][q] = (g > 0 && i < nx) ? xh_row(g - 1, par, 1, s2)[i] : T(0);
+                                T v = T(0);
+                                if (g > 0 && i < nx) {
+                                    const T* src = xh_row(g - 1, par, 1, s2) + i;
+                                    v = xload(src);
+                                }
+                                top[s2][q] = v;
                             }
                     }
                     if (w == NW - 1) {
@@ -310,7 +332,12 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
 #pragma unroll
                             for (int q = 0; q < PX; ++q) {
                                 const int i = lane * PX + q;
-                                bot[s2][q] = (g + 1 < G && i < nx) ? xh_row(g + 1, par, 0, s2)[i] : T(0);
+                                T v = T(0);
+                                if (g + 1 < G && i < nx) {
+                                    const T* src = xh_row(g + 1, par, 0, s2) + i;
+                                    v = xload(src);
+                                }
+                                bot[s2][q] = v;
                             }
                     }
                     T mc = 0, mf = 0;
