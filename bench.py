@@ -245,7 +245,7 @@ def run_mixed(args, w):
             cores = os.cpu_count() or 1
         cores = max(1, min(cores, 16))
         n, paths, K, seed = w.extra[0]
-        per = 4
+        per = 48
         jobs_cpu = [(n, K, seed, i * per, per, w.lo, w.hi, w.order, w.Nf, w.T, w.s0sq, w.a, w.sigma)
                     for i in range(cores)]
         t0 = time.perf_counter()
