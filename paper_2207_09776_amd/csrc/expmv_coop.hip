@@ -9,14 +9,14 @@
 //
 // Per Taylor term the group synchronises once through the workspace:
 //   * the first wave publishes its top RH rows and the last wave its bottom RH
-//     rows (the halo the neighbouring slabs need),
-//   * wave 0 publishes the workgroup's inf-norms of the previous term (or of
-//     the state at the start of a sub-step), then bumps the workgroup's counter
-//     with an agent-scope release store,
-//   * wave 0 waits (acquire) until every member's counter reached the same
-//     value, so every member sees the same norms and takes the same
-//     early-termination decision, and the edge waves read their neighbours'
-//     halo rows.
+//     rows (the halo the neighbouring slabs need), and every wave publishes
+//     its inf-norms of the previous term and partial sum (of the state at the
+//     start of a sub-step); each wave then waits for its own stores,
+//   * after a workgroup barrier wave 0 bumps the workgroup's counter and waits
+//     until every member's counter reached the same value,
+//   * after a second barrier the edge waves load their neighbours' halo rows
+//     and every wave loads the norms of all waves of all members, so every
+//     member takes the same early-termination decision.
 // Waiting is bounded: after kSpinLimit polls the launch is aborted through a
 // shared word, every workgroup leaves its loops and the paths get
 // MG_FLAG_ABORT.
@@ -53,7 +53,7 @@ struct CoopArgs {
     int32_t* flags;
     // exchange area (in the caller's workspace, zeroed before the launch)
     char* xh;          // halo rows   [ngroups][G][2 parity][2 side][RHX][nx] of T
-    double* xn;        // norms       [ngroups][G][2 parity][4]
+    double* xn;        // norms       [ngroups][G][2 parity][NW waves][2]
     int* fl;           // counters    [ngroups][G]
     int* abort_word;
     int G;
@@ -112,8 +112,7 @@ struct HaloC {
 
 template <int PX, int NW, int RH, class T>
 constexpr size_t coop_lds_bytes() {
-    return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + (size_t)2 * NW * 2 * sizeof(T) +
-           (size_t)NW * sizeof(T) + 16;
+    return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + 16;
 }
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C>
@@ -126,9 +125,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     HaloC<PX, RJ, NW, RH, T> halo{lds};
-    T* red = lds + (size_t)NW * 2 * RH * 64 * PX;   // [2][NW][2] term norms
-    T* red2 = red + 2 * NW * 2;                      // [NW] state norms
-    int* sh = reinterpret_cast<int*>(red2 + NW);     // [0] abort
+    int* sh = reinterpret_cast<int*>(lds + (size_t)NW * 2 * RH * 64 * PX);   // [0] abort
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -157,8 +154,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
         return xh + ((((size_t)grp * G + member) * 2 + par) * 2 + side) * (size_t)kRHX * nx +
                (size_t)s * nx;
     };
-    auto xn_at = [&](int member, int par) -> double* {
-        return a.xn + (((size_t)grp * G + member) * 2 + par) * 4;
+    // per member and parity: NW pairs (one per wave) of norms
+    auto xn_at = [&](int member, int par, int wave) -> double* {
+        return a.xn + ((((size_t)grp * G + member) * 2 + par) * NW + wave) * 2;
     };
 
     int counter = 0;      // group syncs done by this launch
@@ -185,22 +183,21 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                     if (i < nx) xstore(xh_row(g, par, 1, s) + i, d[RJ - RH + s][q]);
                 }
         }
-        if (w == 0 || w == NW - 1) wait_stores();
+    };
+    // this wave's pair of norms for the coming sync
+    auto publish_pair = [&](double v0, double v1) {
+        if (lane == 0) {
+            double* x = xn_at(g, counter & 1, w);
+            xstore(x, v0);
+            xstore(x + 1, v1);
+        }
     };
 
-    // One group synchronisation; the caller has executed a barrier after its
-    // LDS and global writes.  Publishes this workgroup's (uniform) payload and
-    // returns the member-wise maxima in out[].
-    auto group_exchange = [&](double p0, double p1, double p2, double (&out)[3]) {
-        const int par = counter & 1;
+    // One group synchronisation.  Every wave has published its pair and its
+    // halo rows and waited for its stores, then the workgroup passed a
+    // barrier; wave 0 bumps the counter and waits for the other members.
+    auto group_sync = [&]() {
         if (w == 0) {
-            if (lane == 0) {
-                double* x = xn_at(g, par);
-                xstore(x, p0);
-                xstore(x + 1, p1);
-                xstore(x + 2, p2);
-            }
-            wait_stores();
             if (lane == 0) xstore(my_cnt, counter + 1);
             // wait until every member published this sync (lane m watches member m)
             int spins = 0;
@@ -217,27 +214,28 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            // the data loads below stay after the counter loads
-            asm volatile("" ::: "memory");
             if (lane == 0) sh[0] = ab ? 1 : 0;
         }
         __syncthreads();
+        // the exchange loads that follow stay after the counter loads
+        asm volatile("" ::: "memory");
         aborted = __builtin_amdgcn_readfirstlane(sh[0]) != 0;
-        double o0 = 0.0, o1 = 0.0, o2 = 0.0;
-        for (int mm = lane; mm < G; mm += 64) {
-            const double* x = xn_at(mm, par);
+    };
+    // Maxima over every wave of every member of the pairs of the sync just done.
+    auto read_pairs = [&](double (&out)[2]) {
+        const int par = counter & 1;
+        double o0 = 0.0, o1 = 0.0;
+        for (int idx = lane; idx < G * NW; idx += 64) {
+            const double* x = xn_at(idx / NW, par, idx % NW);
             o0 = fmax(o0, xload(x));
             o1 = fmax(o1, xload(x + 1));
-            o2 = fmax(o2, xload(x + 2));
         }
         for (int o = 32; o > 0; o >>= 1) {
             o0 = fmax(o0, __shfl_xor(o0, o, 64));
             o1 = fmax(o1, __shfl_xor(o1, o, 64));
-            o2 = fmax(o2, __shfl_xor(o2, o, 64));
         }
         out[0] = uniform(o0);
         out[1] = uniform(o1);
-        out[2] = uniform(o2);
         ++counter;
     };
 
@@ -277,41 +275,25 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                         sm = max_abs(sm, F[r][q]);
                     }
                 sm = wave_max(sm);
-                if (lane == 0) red2[w] = sm;
+                // this wave's pair for the next sync: the state norm (first
+                // term), then the norms of the previous term and partial sum
+                double pr0 = (double)uniform(sm), pr1 = 0.0;
                 double c1 = 0.0;
                 T fj = 1;
                 for (int j = 1; j <= m; ++j) {
                     const int par = counter & 1;
                     halo.publish(w, lane, d);
                     publish_global(d);
+                    publish_pair(pr0, pr1);
+                    wait_stores();
                     __syncthreads();
+                    // LDS halo read between the two barriers (the next term
+                    // writes it after the second)
                     T top[RH][PX], bot[RH][PX];
                     halo.fetch(w, lane, top, bot);
-                    // payload: the state norm (j = 1) or the norms of term j-1
-                    double pay0 = 0.0, pay1 = 0.0, got[3];
-                    if (j == 1) {
-                        T x = 0;
-                        for (int i = 0; i < NW; ++i) x = max_abs(x, red2[i]);
-                        pay0 = (double)uniform(x);
-                    } else {
-                        T c2 = 0, fn = 0;
-                        const T* rr = red + (size_t)(par ^ 1) * NW * 2;
-                        for (int i = 0; i < NW; ++i) {
-                            c2 = max_abs(c2, rr[2 * i]);
-                            fn = max_abs(fn, rr[2 * i + 1]);
-                        }
-                        pay0 = (double)uniform(c2);
-                        pay1 = (double)uniform(fn);
-                    }
-                    group_exchange(pay0, pay1, 0.0, got);
+                    group_sync();
                     if (aborted) break;
-                    if (j == 1) {
-                        c1 = got[0];
-                    } else {
-                        const double c2 = got[0], fn = got[1];
-                        if (c1 + c2 <= a.tol * fn) break;
-                        c1 = c2;
-                    }
+                    // neighbours' halo rows and the pairs, loaded together
                     if (w == 0) {
 #pragma unroll
                         for (int s2 = 0; s2 < RH; ++s2)
@@ -319,10 +301,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                             for (int q = 0; q < PX; ++q) {
                                 const int i = lane * PX + q;
                                 T v = T(0);
-                                if (g > 0 && i < nx) {
-                                    const T* src = xh_row(g - 1, par, 1, s2) + i;
-                                    v = xload(src);
-                                }
+                                if (g > 0 && i < nx) v = xload(xh_row(g - 1, par, 1, s2) + i);
                                 top[s2][q] = v;
                             }
                     }
@@ -333,12 +312,18 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                             for (int q = 0; q < PX; ++q) {
                                 const int i = lane * PX + q;
                                 T v = T(0);
-                                if (g + 1 < G && i < nx) {
-                                    const T* src = xh_row(g + 1, par, 0, s2) + i;
-                                    v = xload(src);
-                                }
+                                if (g + 1 < G && i < nx) v = xload(xh_row(g + 1, par, 0, s2) + i);
                                 bot[s2][q] = v;
                             }
+                    }
+                    double got[2];
+                    read_pairs(got);
+                    if (j == 1) {
+                        c1 = got[0];
+                    } else {
+                        const double c2 = got[0], fn = got[1];
+                        if (c1 + c2 <= a.tol * fn) break;
+                        c1 = c2;
                     }
                     T mc = 0, mf = 0;
                     if constexpr (F32C) {
@@ -374,10 +359,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                         mc = wave_max(mc) * fj;
                     }
                     mf = wave_max(mf);
-                    if (lane == 0) {
-                        red[(size_t)par * NW * 2 + 2 * w] = mc;
-                        red[(size_t)par * NW * 2 + 2 * w + 1] = mf;
-                    }
+                    pr0 = (double)mc;
+                    pr1 = (double)mf;
                     ++terms;
                 }
 #pragma unroll
@@ -413,10 +396,16 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                 }
             }
         const int any_bad = __syncthreads_or(bad ? 1 : 0);
-        double got[3] = {0.0, 0.0, 0.0};
-        if (!aborted) group_exchange(0.0, 0.0, any_bad ? 1.0 : 0.0, got);
+        double got[2] = {0.0, 0.0};
+        if (!aborted) {
+            publish_pair(any_bad ? 1.0 : 0.0, 0.0);
+            wait_stores();
+            __syncthreads();
+            group_sync();
+            if (!aborted) read_pairs(got);
+        }
         if (a.flags && g == 0 && threadIdx.x == 0) {
-            int f = pflag | (got[2] != 0.0 ? MG_FLAG_NONFINITE : 0);
+            int f = pflag | (got[0] != 0.0 ? MG_FLAG_NONFINITE : 0);
             if (aborted) f |= MG_FLAG_ABORT;
             a.flags[p] = f;
         }
@@ -546,7 +535,7 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     plan->lds = lds;
     plan->threads = 64 * sh.NW;
     plan->xh_bytes = ((size_t)ngroups * G * 2 * 2 * kRHX * ops->grid.nx * elem + 255) & ~(size_t)255;
-    plan->xn_bytes = ((size_t)ngroups * G * 2 * 4 * sizeof(double) + 255) & ~(size_t)255;
+    plan->xn_bytes = ((size_t)ngroups * G * 2 * sh.NW * 2 * sizeof(double) + 255) & ~(size_t)255;
     plan->fl_bytes = ((size_t)ngroups * G * sizeof(int) + 256 + 255) & ~(size_t)255;
     plan->bytes = plan->xh_bytes + plan->xn_bytes + plan->fl_bytes;
     return hipSuccess;
