@@ -220,11 +220,19 @@ mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t N
  * with the B and A of `ops` (built at any order).
  *   u     : device FP64 [P][N], updated in place.
  *   dWE   : device FP64 [P][NE], the Brownian increment of each Euler step.
- *   flags : device int32 [P] or NULL (MG_FLAG_NONFINITE).
- *   precision must be MG_FP64.  ws/ws_bytes are reserved (pass NULL, 0).
- * Errors: MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP.  P = 0 or NE = 0
- * is a no-op.
+ *   flags : device int32 [P] or NULL (MG_FLAG_NONFINITE; MG_FLAG_ABORT if
+ *           the workgroups sharing a path stopped waiting for each other).
+ *   precision must be MG_FP64.
+ *   ws    : device workspace of ws_bytes >= mg_euler_workspace_bytes(ops, P)
+ *           (the exchange area of grids with nx > 128, where several
+ *           workgroups share a path); may be NULL when that size is 0.
+ * Errors: MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED (nx > 512), MG_ENOMEM (ws
+ * too small), MG_EHIP.  P = 0 or NE = 0 is a no-op.
  * ------------------------------------------------------------------------ */
+/* Bytes of device workspace mg_euler_step needs for P paths (0 for grids
+ * with nx, nv <= 128; (size_t)-1 if no Euler kernel fits the grid). */
+size_t mg_euler_workspace_bytes(const mg_ops* ops, int64_t P);
+
 mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* dWE, int32_t NE,
                         double dt, int32_t precision, void* ws, size_t ws_bytes, int32_t* flags,
                         void* stream);

@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_workspace_bytes", "mg_magnus_expmv", "mg_workspace_bytes_multi",
-           "mg_magnus_expmv_multi", "mg_euler_increments", "mg_euler_step",
+           "mg_magnus_expmv_multi", "mg_euler_increments", "mg_euler_workspace_bytes",
+           "mg_euler_step",
            "mg_error_vs_exact",
            "mg_last_error", "mg_timing_enable", "mg_timing_read", "mg_timing_reset", "mg_version")
 
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_iterated_integrals.argtypes = [vp, i64, i64, dbl, i32, i32, vp, vp, vp]
     lib.mg_workspace_bytes.argtypes = [vp, i64, i32, i32]
     lib.mg_workspace_bytes.restype = sz
+    lib.mg_euler_workspace_bytes.argtypes = [vp, i64]
+    lib.mg_euler_workspace_bytes.restype = sz
     lib.mg_magnus_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, vp, vp, vp]
     lib.mg_workspace_bytes_multi.argtypes = [ctypes.POINTER(mg_job), i32]
     lib.mg_workspace_bytes_multi.restype = sz
@@ -266,15 +269,28 @@ def euler_increments(dW, NE: int, dWE=None, stream=None):
     return dWE
 
 
-def euler_step(ops: Operators, u, dWE, dt: float, stream=None):
+def euler_workspace_bytes(ops: Operators, P: int) -> int:
+    """mg_euler_workspace_bytes (raises MagnusError if no Euler kernel fits)."""
+    n = int(load_library().mg_euler_workspace_bytes(ops.handle, P))
+    if n == ctypes.c_size_t(-1).value:
+        raise MagnusError(MG_EUNSUPPORTED, "mg_euler_workspace_bytes: no Euler kernel for this grid")
+    return n
+
+
+def euler_step(ops: Operators, u, dWE, dt: float, ws=None, stream=None):
     """mg_euler_step: NE Euler-Maruyama steps in place on u [P][N]; returns flags."""
     import torch
     _dev_f64(u, "u")
     _dev_f64(dWE, "dWE")
     P, NE = dWE.shape
     flags = torch.zeros(P, dtype=torch.int32, device=u.device)
+    if ws is None:
+        need = euler_workspace_bytes(ops, P)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=u.device) if need else None
     _check(load_library().mg_euler_step(ops.handle, _ptr(u), P, _ptr(dWE), NE, float(dt), MG_FP64,
-                                        None, 0, _ptr(flags), _stream(stream)))
+                                        _ptr(ws) if ws is not None else None,
+                                        ws.numel() if ws is not None else 0, _ptr(flags),
+                                        _stream(stream)))
     return flags
 
 

@@ -159,8 +159,7 @@ Family family_of(const mg_ops* ops, int precision) {
     if (launch_expmv_resident(ops, nullptr, 0, 1, 1, nullptr, 0, nullptr, 0.0, precision, nullptr,
                               nullptr, nullptr, true) == hipSuccess)
         return Family::Resident;
-    // the cooperative kernel does not take x-dependent factors
-    if (coop_rows_per_group_member(ops->grid.nx) > 0 && ops->ND == 0) return Family::Coop;
+    if (coop_supported(ops, precision)) return Family::Coop;
     return Family::None;
 }
 }  // namespace
@@ -209,8 +208,9 @@ mg_status expmv_prepare(ExpmvCall& c, const std::string& where) {
     c.fam = family_of(c.ops, c.precision);
     if (c.fam == Family::None)
         return mg_fail(MG_EUNSUPPORTED,
-                       where + (c.ops->ND > 0 ? ": x-dependent coefficients need nx, nv <= 128"
-                                              : ": no kernel for this grid size"));
+                       where + (c.ops->ND > 0
+                                    ? ": x-dependent coefficients need nx <= 512 (orders 1, 2)"
+                                    : ": no kernel for this grid size and precision"));
     if (c.P == 0) return MG_OK;
     if (!c.coef || !c.u0 || !c.uT) return mg_fail(MG_EINVAL, where + ": NULL pointer");
     if (c.fam == Family::Coop) {
@@ -312,11 +312,30 @@ mg_status mg_magnus_expmv_multi(const mg_job* jobs, int32_t njobs, void* ws, siz
     return MG_OK;
 }
 
+namespace {
+// Euler kernel family: resident (nx, nv <= 128) or cooperative (nx <= 512)
+Family euler_family(const mg_ops* ops) {
+    if (launch_euler_resident(ops, nullptr, 1, nullptr, 1, 0.0, nullptr, nullptr, true) ==
+        hipSuccess)
+        return Family::Resident;
+    if (coop_supported(ops, MG_FP64, CoopKind::Euler)) return Family::Coop;
+    return Family::None;
+}
+}  // namespace
+
+size_t mg_euler_workspace_bytes(const mg_ops* ops, int64_t P) {
+    if (!ops || P < 0) return (size_t)-1;
+    const Family f = euler_family(ops);
+    if (f == Family::None) return (size_t)-1;
+    if (f == Family::Resident || P == 0) return 0;
+    CoopPlan plan;
+    if (coop_plan(ops, MG_FP64, P, &plan, CoopKind::Euler) != hipSuccess) return (size_t)-1;
+    return plan.bytes;
+}
+
 mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* dWE, int32_t NE,
                         double dt, int32_t precision, void* ws, size_t ws_bytes, int32_t* flags,
                         void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     g_last_error.clear();
     if (!ops) return mg_fail(MG_EINVAL, "mg_euler_step: NULL ops");
     if (P < 0 || NE < 0) return mg_fail(MG_ESHAPE, "mg_euler_step: need P >= 0 and NE >= 0");
@@ -324,12 +343,24 @@ mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* d
     if (precision != MG_FP64) return mg_fail(MG_EUNSUPPORTED, "mg_euler_step: only MG_FP64");
     if (!is_finite(dt)) return mg_fail(MG_EINVAL, "mg_euler_step: dt must be finite");
     hipStream_t s = (hipStream_t)stream;
-    if (launch_euler_resident(ops, nullptr, P, nullptr, NE, dt, nullptr, s, true) != hipSuccess)
+    const Family fam = euler_family(ops);
+    if (fam == Family::None)
         return mg_fail(MG_EUNSUPPORTED, "mg_euler_step: no kernel for this grid size");
     if (P == 0 || NE == 0) return MG_OK;
     if (!u || !dWE) return mg_fail(MG_EINVAL, "mg_euler_step: NULL pointer");
+    CoopPlan plan;
+    if (fam == Family::Coop) {
+        hipError_t e = coop_plan(ops, MG_FP64, P, &plan, CoopKind::Euler);
+        if (e != hipSuccess) return hip_fail(e, "mg_euler_step: cooperative plan");
+        if (!ws || ws_bytes < plan.bytes)
+            return mg_fail(MG_ENOMEM, "mg_euler_step: workspace too small (need " +
+                                          std::to_string(plan.bytes) + " bytes)");
+    }
     TimingScope ts("euler", s);
-    hipError_t e = launch_euler_resident(ops, u, P, dWE, NE, dt, flags, s, false);
+    hipError_t e = fam == Family::Resident
+                       ? launch_euler_resident(ops, u, P, dWE, NE, dt, flags, s, false)
+                       : launch_euler_coop(ops, u, P, dWE, NE, dt, flags,
+                                           static_cast<char*>(ws), plan, s);
     ts.done();
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_euler_step");
 }

@@ -40,6 +40,18 @@ using namespace mgk;
 
 constexpr int kSpinLimit = 1 << 22;
 
+// Exchange area of a cooperative launch (in the caller's workspace, zeroed
+// before the launch) and the group layout.
+struct XArea {
+    char* xh;          // halo rows   [ngroups][G][2 parity][2 side][RHX][nx] of T
+    double* xn;        // norms       [ngroups][G][2 parity][NW waves][2]
+    int* fl;           // counters    [ngroups][G]
+    int* abort_word;
+    int G;             // workgroups per path
+    int ngroups;
+    int xcd_map;       // members of a group on one XCD (blockIdx mod 8)
+};
+
 struct CoopArgs {
     const char* tables;
     size_t tbytes;
@@ -51,14 +63,21 @@ struct CoopArgs {
     double tol;
     int32_t* stats;
     int32_t* flags;
-    // exchange area (in the caller's workspace, zeroed before the launch)
-    char* xh;          // halo rows   [ngroups][G][2 parity][2 side][RHX][nx] of T
-    double* xn;        // norms       [ngroups][G][2 parity][NW waves][2]
-    int* fl;           // counters    [ngroups][G]
-    int* abort_word;
-    int G;
-    int ngroups;
-    int xcd_map;       // members of a group on one XCD (blockIdx mod 8)
+    const double* xdiag;   // x vectors of the x-dependent factors [ND][nx]
+    XArea x;
+};
+
+struct EulerCoopArgs {
+    const double* basis;   // operator tables (B is basis matrix 0, A matrix 1)
+    int nx, nv, nv_pad;
+    int64_t P;
+    double* u;             // [P][nv][nx], updated in place
+    const double* dWE;     // [P][NE]
+    int NE;
+    double dt;
+    int32_t* flags;
+    const double* xdiag;
+    XArea x;
 };
 
 // Stores issued so far by this wave have completed (device-coherent stores
@@ -110,60 +129,44 @@ struct HaloC {
     }
 };
 
-template <int PX, int NW, int RH, class T>
-constexpr size_t coop_lds_bytes() {
-    return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + 16;
-}
-
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C>
-__global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
-    using T = typename std::conditional<F32C, float, double>::type;
-    using BD = Bands<R0, R1, R2>;
-    constexpr int RH = BD::RH > 0 ? BD::RH : 1;
-    constexpr int NBP = BD::NBP;
-    constexpr int RW = NW * RJ;
-    extern __shared__ double lds_d[];
-    T* lds = reinterpret_cast<T*>(lds_d);
-    HaloC<PX, RJ, NW, RH, T> halo{lds};
-    int* sh = reinterpret_cast<int*>(lds + (size_t)NW * 2 * RH * 64 * PX);   // [0] abort
-
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int G = a.G;
-    int g, grp;
-    {
-        const int b = blockIdx.x;
-        if (a.xcd_map) {
-            const int xcd = b & 7, k = b >> 3;
-            g = k % G;
-            grp = (k / G) * 8 + xcd;
-        } else {
-            g = b % G;
-            grp = b / G;
-        }
-    }
-    const int nx = a.nx, nv = a.nv;
-    const size_t N = (size_t)nx * nv;
-    const int row0 = g * RW + w * RJ;                 // first global row of this wave
-    const int nrows = min(RJ, max(0, nv - row0));
-
-    int* my_cnt = a.fl + (size_t)grp * G + g;
-    const int* grp_cnt = a.fl + (size_t)grp * G;
-    T* xh = reinterpret_cast<T*>(a.xh);
-    auto xh_row = [&](int member, int par, int side, int s) -> T* {
-        return xh + ((((size_t)grp * G + member) * 2 + par) * 2 + side) * (size_t)kRHX * nx +
-               (size_t)s * nx;
-    };
-    // per member and parity: NW pairs (one per wave) of norms
-    auto xn_at = [&](int member, int par, int wave) -> double* {
-        return a.xn + ((((size_t)grp * G + member) * 2 + par) * NW + wave) * 2;
-    };
-
+// One workgroup's view of its group: slab index g, group index grp, the
+// exchange through the workspace and the count of group synchronisations.
+// Per synchronisation: every wave publishes (publish_edges, publish_pair) and
+// waits for its stores, the workgroup passes a barrier, then sync() bumps this
+// member's counter and waits for the others; load_edges and read_pairs read
+// what the neighbours published, and next() closes the synchronisation.
+template <int PX, int RJ, int NW, int RH, class T>
+struct CoopGroup {
+    XArea x;
+    int lane, w, nx, g, grp;
+    int* sh;              // LDS word: abort seen by wave 0
     int counter = 0;      // group syncs done by this launch
     bool aborted = false;
 
-    // Edge rows of d for the neighbouring slabs (parity of the coming sync).
-    auto publish_global = [&](const T (&d)[RJ][PX]) {
+    __device__ __forceinline__ CoopGroup(const XArea& xa, int nx_, int* sh_) : x(xa), nx(nx_), sh(sh_) {
+        lane = threadIdx.x & 63;
+        w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int b = blockIdx.x;
+        if (x.xcd_map) {
+            const int xcd = b & 7, k = b >> 3;
+            g = k % x.G;
+            grp = (k / x.G) * 8 + xcd;
+        } else {
+            g = b % x.G;
+            grp = b / x.G;
+        }
+    }
+    __device__ __forceinline__ T* xh_row(int member, int par, int side, int s) const {
+        return reinterpret_cast<T*>(x.xh) +
+               ((((size_t)grp * x.G + member) * 2 + par) * 2 + side) * (size_t)kRHX * nx +
+               (size_t)s * nx;
+    }
+    // per member and parity: NW pairs (one per wave) of norms
+    __device__ __forceinline__ double* xn_at(int member, int par, int wave) const {
+        return x.xn + ((((size_t)grp * x.G + member) * 2 + par) * NW + wave) * 2;
+    }
+    // edge rows of d for the neighbouring slabs (parity of the coming sync)
+    __device__ __forceinline__ void publish_edges(const T (&d)[RJ][PX]) const {
         const int par = counter & 1;
         if (w == 0 && g > 0) {
 #pragma unroll
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                     if (i < nx) xstore(xh_row(g, par, 0, s) + i, d[s][q]);
                 }
         }
-        if (w == NW - 1 && g + 1 < G) {
+        if (w == NW - 1 && g + 1 < x.G) {
 #pragma unroll
             for (int s = 0; s < RH; ++s)
 #pragma unroll
@@ -183,33 +186,30 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                     if (i < nx) xstore(xh_row(g, par, 1, s) + i, d[RJ - RH + s][q]);
                 }
         }
-    };
+    }
     // this wave's pair of norms for the coming sync
-    auto publish_pair = [&](double v0, double v1) {
+    __device__ __forceinline__ void publish_pair(double v0, double v1) const {
         if (lane == 0) {
-            double* x = xn_at(g, counter & 1, w);
-            xstore(x, v0);
-            xstore(x + 1, v1);
+            double* p = xn_at(g, counter & 1, w);
+            xstore(p, v0);
+            xstore(p + 1, v1);
         }
-    };
-
-    // One group synchronisation.  Every wave has published its pair and its
-    // halo rows and waited for its stores, then the workgroup passed a
-    // barrier; wave 0 bumps the counter and waits for the other members.
-    auto group_sync = [&]() {
+    }
+    // wave 0 bumps the counter and waits (bounded) for every member
+    __device__ __forceinline__ void sync() {
         if (w == 0) {
-            if (lane == 0) xstore(my_cnt, counter + 1);
-            // wait until every member published this sync (lane m watches member m)
+            if (lane == 0) xstore(x.fl + (size_t)grp * x.G + g, counter + 1);
+            const int* cnt = x.fl + (size_t)grp * x.G;
             int spins = 0;
             bool ab = false;
             for (;;) {
                 bool ready = true;
-                for (int mm = lane; mm < G; mm += 64)
-                    if (xload(grp_cnt + mm) < counter + 1) ready = false;
+                for (int mm = lane; mm < x.G; mm += 64)
+                    if (xload(cnt + mm) < counter + 1) ready = false;
                 if (__all(ready)) break;
-                if (++spins > kSpinLimit || xload(a.abort_word)) {
+                if (++spins > kSpinLimit || xload(x.abort_word)) {
                     ab = true;
-                    if (lane == 0) xstore(a.abort_word, 1);
+                    if (lane == 0) xstore(x.abort_word, 1);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -220,15 +220,43 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
         // the exchange loads that follow stay after the counter loads
         asm volatile("" ::: "memory");
         aborted = __builtin_amdgcn_readfirstlane(sh[0]) != 0;
-    };
-    // Maxima over every wave of every member of the pairs of the sync just done.
-    auto read_pairs = [&](double (&out)[2]) {
+    }
+    // the neighbours' edge rows into the outer halo rows of the edge waves
+    // (the bottom rows are written through selects: two alike branches would
+    // be merged into stores through a pointer, which moves the arrays to
+    // scratch memory)
+    __device__ __forceinline__ void load_edges(T (&top)[RH][PX], T (&bot)[RH][PX]) const {
+        const int par = counter & 1;
+        if (w == 0) {
+#pragma unroll
+            for (int s = 0; s < RH; ++s)
+#pragma unroll
+                for (int q = 0; q < PX; ++q) {
+                    const int i = lane * PX + q;
+                    T v = T(0);
+                    if (g > 0 && i < nx) v = xload(xh_row(g - 1, par, 1, s) + i);
+                    top[s][q] = v;
+                }
+        }
+        const bool last = w == NW - 1;
+#pragma unroll
+        for (int s = 0; s < RH; ++s)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                const int i = lane * PX + q;
+                T v = T(0);
+                if (last && g + 1 < x.G && i < nx) v = xload(xh_row(g + 1, par, 0, s) + i);
+                bot[s][q] = last ? v : bot[s][q];
+            }
+    }
+    // maxima over every wave of every member of the pairs of this sync
+    __device__ __forceinline__ void read_pairs(double (&out)[2]) const {
         const int par = counter & 1;
         double o0 = 0.0, o1 = 0.0;
-        for (int idx = lane; idx < G * NW; idx += 64) {
-            const double* x = xn_at(idx / NW, par, idx % NW);
-            o0 = fmax(o0, xload(x));
-            o1 = fmax(o1, xload(x + 1));
+        for (int idx = lane; idx < x.G * NW; idx += 64) {
+            const double* p = xn_at(idx / NW, par, idx % NW);
+            o0 = fmax(o0, xload(p));
+            o1 = fmax(o1, xload(p + 1));
         }
         for (int o = 32; o > 0; o >>= 1) {
             o0 = fmax(o0, __shfl_xor(o0, o, 64));
@@ -236,10 +264,110 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
         }
         out[0] = uniform(o0);
         out[1] = uniform(o1);
-        ++counter;
+    }
+    __device__ __forceinline__ void next() { ++counter; }
+    // end of a path: combine a per-workgroup flag over the group (nonzero if
+    // any member set it)
+    __device__ __forceinline__ bool any_member(bool mine) {
+        const int any = __syncthreads_or(mine ? 1 : 0);
+        if (aborted) return false;
+        publish_pair(any ? 1.0 : 0.0, 0.0);
+        wait_stores();
+        __syncthreads();
+        sync();
+        if (aborted) return false;
+        double got[2];
+        read_pairs(got);
+        next();
+        return got[0] != 0.0;
+    }
+};
+
+// x vectors of the x-dependent factors: registers in FP32, LDS in FP64 (the
+// FP64 state, halo and factors together exceed the register file)
+template <int ND, class T>
+constexpr bool xa_in_lds() {
+    return ND > 0 && sizeof(T) == 8;
+}
+
+// LDS: halo | abort word (16 bytes) | x vectors [ND][64*PX] (when in LDS)
+template <int PX, int NW, int RH, int ND, class T>
+constexpr size_t coop_lds_bytes() {
+    return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + 16 +
+           (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX * sizeof(T) : 0);
+}
+
+// The x vectors at this lane's points (zero beyond nx), in registers or in LDS
+// (written by wave 0; the caller passes a barrier before the first use).
+template <int PX, int ND, bool LDS, class T>
+struct XVec;
+template <int PX, int ND, class T>
+struct XVec<PX, ND, false, T> {
+    static constexpr int NDX = ND > 0 ? ND : 1;
+    T v[NDX][PX];
+    __device__ __forceinline__ XVec(const double* xdiag, T*, int lane, int nx) {
+#pragma unroll
+        for (int t = 0; t < NDX; ++t)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                const int i = lane * PX + q;
+                v[t][q] = (ND > 0 && i < nx) ? (T)xdiag[(size_t)t * nx + i] : T(0);
+            }
+    }
+    __device__ __forceinline__ T operator()(int t, int q) const { return v[t][q]; }
+};
+template <int PX, int ND, class T>
+struct XVec<PX, ND, true, T> {
+    const T* xs;
+    int lane;
+    __device__ __forceinline__ XVec(const double* xdiag, T* lds, int lane_, int nx)
+        : xs(lds), lane(lane_) {
+        if (threadIdx.x < 64) {
+            for (int t = 0; t < ND; ++t)
+#pragma unroll
+                for (int q = 0; q < PX; ++q) {
+                    const int i = lane * PX + q;
+                    lds[t * 64 * PX + lane * PX + q] = i < nx ? (T)xdiag[(size_t)t * nx + i] : T(0);
+                }
+        }
+    }
+    __device__ __forceinline__ T operator()(int t, int q) const {
+        return xs[t * 64 * PX + lane * PX + q];
+    }
+};
+
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
+__global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
+    using T = typename std::conditional<F32C, float, double>::type;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int RW = NW * RJ;
+    extern __shared__ double lds_d[];
+    T* lds = reinterpret_cast<T*>(lds_d);
+    HaloC<PX, RJ, NW, RH, T> halo{lds};
+    CoopGroup<PX, RJ, NW, RH, T> cg(a.x, a.nx, reinterpret_cast<int*>(lds + (size_t)NW * 2 * RH * 64 * PX));
+    const int lane = cg.lane, w = cg.w, g = cg.g, grp = cg.grp;
+    const int nx = a.nx, nv = a.nv;
+    const size_t N = (size_t)nx * nv;
+    const int row0 = g * RW + w * RJ;                 // first global row of this wave
+    const int nrows = min(RJ, max(0, nv - row0));
+    // the x vectors of the x-dependent factors at this lane's points
+    const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(
+        a.xdiag, lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T), lane, nx);
+    __syncthreads();
+
+    // one application of the operator to this wave's rows, in place
+    auto apply_term = [&](T (&d)[RJ][PX], const T (&top)[RH][PX], const T (&bot)[RH][PX],
+                          auto coef, auto emit) {
+        if constexpr (ND == 0)
+            apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef, lane, nx,
+                                                                  emit);
+        else
+            apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
+                d, top, bot, coef, xa, lane, nx, emit);
     };
 
-    for (int64_t p = grp; p < a.P && !aborted; p += a.ngroups) {
+    for (int64_t p = grp; p < a.P && !cg.aborted; p += a.x.ngroups) {
         // state F (+ compensation L for the FP32 form)
         T F[RJ][PX], L[RJ][PX];
         {
@@ -255,7 +383,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                 }
         }
         int pflag = 0;
-        for (int k = 0; k < a.K && !aborted; ++k) {
+        for (int k = 0; k < a.K && !cg.aborted; ++k) {
             const TableView tv{a.tables + ((size_t)p * a.K + k) * a.tbytes};
             const int s = tv.s();
             const int m = tv.m();
@@ -264,7 +392,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
             const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
             auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
             int terms = 0;
-            for (int sub = 0; sub < s && !aborted; ++sub) {
+            for (int sub = 0; sub < s && !cg.aborted; ++sub) {
                 T d[RJ][PX];
                 T sm = 0;
 #pragma unroll
@@ -281,43 +409,22 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                 double c1 = 0.0;
                 T fj = 1;
                 for (int j = 1; j <= m; ++j) {
-                    const int par = counter & 1;
                     halo.publish(w, lane, d);
-                    publish_global(d);
-                    publish_pair(pr0, pr1);
+                    cg.publish_edges(d);
+                    cg.publish_pair(pr0, pr1);
                     wait_stores();
                     __syncthreads();
                     // LDS halo read between the two barriers (the next term
                     // writes it after the second)
                     T top[RH][PX], bot[RH][PX];
                     halo.fetch(w, lane, top, bot);
-                    group_sync();
-                    if (aborted) break;
+                    cg.sync();
+                    if (cg.aborted) break;
                     // neighbours' halo rows and the pairs, loaded together
-                    if (w == 0) {
-#pragma unroll
-                        for (int s2 = 0; s2 < RH; ++s2)
-#pragma unroll
-                            for (int q = 0; q < PX; ++q) {
-                                const int i = lane * PX + q;
-                                T v = T(0);
-                                if (g > 0 && i < nx) v = xload(xh_row(g - 1, par, 1, s2) + i);
-                                top[s2][q] = v;
-                            }
-                    }
-                    if (w == NW - 1) {
-#pragma unroll
-                        for (int s2 = 0; s2 < RH; ++s2)
-#pragma unroll
-                            for (int q = 0; q < PX; ++q) {
-                                const int i = lane * PX + q;
-                                T v = T(0);
-                                if (g + 1 < G && i < nx) v = xload(xh_row(g + 1, par, 0, s2) + i);
-                                bot[s2][q] = v;
-                            }
-                    }
+                    cg.load_edges(top, bot);
                     double got[2];
-                    read_pairs(got);
+                    cg.read_pairs(got);
+                    cg.next();
                     if (j == 1) {
                         c1 = got[0];
                     } else {
@@ -341,8 +448,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                                 mf = max_abs(mf, t);
                             }
                         };
-                        apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef,
-                                                                              lane, nx, emit);
+                        apply_term(d, top, bot, coef, emit);
                         mc = wave_max(mc);
                     } else {
                         fj /= (T)j;
@@ -354,8 +460,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                                 mf = max_abs(mf, F[r][q]);
                             }
                         };
-                        apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef,
-                                                                              lane, nx, emit);
+                        apply_term(d, top, bot, coef, emit);
                         mc = wave_max(mc) * fj;
                     }
                     mf = wave_max(mf);
@@ -395,24 +500,101 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                     bad |= !isfinite(u);
                 }
             }
-        const int any_bad = __syncthreads_or(bad ? 1 : 0);
-        double got[2] = {0.0, 0.0};
-        if (!aborted) {
-            publish_pair(any_bad ? 1.0 : 0.0, 0.0);
-            wait_stores();
-            __syncthreads();
-            group_sync();
-            if (!aborted) read_pairs(got);
-        }
+        const bool any_bad = cg.any_member(bad);
         if (a.flags && g == 0 && threadIdx.x == 0) {
-            int f = pflag | (got[0] != 0.0 ? MG_FLAG_NONFINITE : 0);
-            if (aborted) f |= MG_FLAG_ABORT;
+            int f = pflag | (any_bad ? MG_FLAG_NONFINITE : 0);
+            if (cg.aborted) f |= MG_FLAG_ABORT;
             a.flags[p] = f;
         }
     }
-    if (aborted && a.flags && threadIdx.x == 0) {
+    if (cg.aborted && a.flags && threadIdx.x == 0) {
         // mark every path this group had not finished
-        for (int64_t p = grp; p < a.P; p += a.ngroups) atomicOr(&a.flags[p], MG_FLAG_ABORT);
+        for (int64_t p = grp; p < a.P; p += a.x.ngroups) atomicOr(&a.flags[p], MG_FLAG_ABORT);
+    }
+}
+
+// Euler-Maruyama on the cooperative layout: u <- u + (dt B + dW_n A) u for
+// n = 0..NE-1 (FP64), one group synchronisation per step for the halo rows.
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
+__global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
+    using T = double;
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int RW = NW * RJ;
+    extern __shared__ double lds_d[];
+    T* lds = lds_d;
+    HaloC<PX, RJ, NW, RH, T> halo{lds};
+    CoopGroup<PX, RJ, NW, RH, T> cg(a.x, a.nx, reinterpret_cast<int*>(lds + (size_t)NW * 2 * RH * 64 * PX));
+    const int lane = cg.lane, w = cg.w, g = cg.g, grp = cg.grp;
+    const int nx = a.nx, nv = a.nv;
+    const size_t N = (size_t)nx * nv;
+    const int row0 = g * RW + w * RJ;
+    const int nrows = min(RJ, max(0, nv - row0));
+    const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(
+        a.xdiag, lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T), lane, nx);
+    __syncthreads();
+    const double* Brows = a.basis + (size_t)row0 * NBP;                  // basis matrix 0: B
+    const double* Arows = a.basis + ((size_t)a.nv_pad + row0) * NBP;     // basis matrix 1: A
+
+    for (int64_t p = grp; p < a.P && !cg.aborted; p += a.x.ngroups) {
+        double* src = a.u + (size_t)p * N;
+        T d[RJ][PX];
+#pragma unroll
+        for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                const int i = lane * PX + q;
+                d[r][q] = (r < nrows && i < nx) ? src[(size_t)(row0 + r) * nx + i] : 0.0;
+            }
+        const double* dw = a.dWE + (size_t)p * a.NE;
+        for (int n = 0; n < a.NE; ++n) {
+            const double wn = dw[n];
+            auto coef = [&](int r, int e) -> T {
+                return fma(a.dt, Brows[r * NBP + e], wn * Arows[r * NBP + e]);
+            };
+            halo.publish(w, lane, d);
+            cg.publish_edges(d);
+            wait_stores();
+            __syncthreads();
+            T top[RH][PX], bot[RH][PX];
+            halo.fetch(w, lane, top, bot);
+            cg.sync();
+            if (cg.aborted) break;
+            cg.load_edges(top, bot);
+            cg.next();
+            // the new row is the old row plus the operator's row (the old row
+            // is still in d when it is emitted)
+            auto emit = [&](int r, T (&y)[PX]) {
+#pragma unroll
+                for (int q = 0; q < PX; ++q) y[q] += d[r][q];
+            };
+            if constexpr (ND == 0)
+                apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef, lane, nx,
+                                                                      emit);
+            else
+                apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
+                    d, top, bot, coef, xa, lane, nx, emit);
+        }
+        bool bad = false;
+#pragma unroll
+        for (int r = 0; r < RJ; ++r)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                const int i = lane * PX + q;
+                if (r < nrows && i < nx) {
+                    src[(size_t)(row0 + r) * nx + i] = d[r][q];
+                    bad |= !isfinite(d[r][q]);
+                }
+            }
+        const bool any_bad = cg.any_member(bad);
+        if (a.flags && g == 0 && threadIdx.x == 0) {
+            int f = any_bad ? MG_FLAG_NONFINITE : 0;
+            if (cg.aborted) f |= MG_FLAG_ABORT;
+            a.flags[p] = f;
+        }
+    }
+    if (cg.aborted && a.flags && threadIdx.x == 0) {
+        for (int64_t p = grp; p < a.P; p += a.x.ngroups) atomicOr(&a.flags[p], MG_FLAG_ABORT);
     }
 }
 
@@ -436,19 +618,32 @@ bool pick_coop_shape(int nx, CoopShape& sh) {
     return false;
 }
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
 hipError_t coop_kernel_info(const void** fn, size_t* lds) {
     using T = typename std::conditional<F32C, float, double>::type;
-    constexpr int RH = Bands<R0, R1, R2>::RH > 0 ? Bands<R0, R1, R2>::RH : 1;
-    *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C>;
-    *lds = coop_lds_bytes<PX, NW, RH, T>();
+    constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND>;
+    *lds = coop_lds_bytes<PX, NW, RH, ND, T>();
     return hipSuccess;
 }
 
 #define MG_COOP_SHAPES(PX, RJ, FULLX, F32C, CALL)                                              \
-    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, 8, 2, 1, 1, 2, FULLX, F32C); \
+    if (ops->ND > 0) return hipErrorInvalidValue;                                              \
+    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, 8, 2, 1, 1, 2, FULLX, F32C, 0); \
+    return hipErrorInvalidValue;
+
+// with x-dependent factors (ND > 0): the order-1 and order-2 shapes, nx <= 512
+#define MG_COOP_SHAPES_X(PX, RJ, FULLX, F32C, CALL)                                            \
+    if (ops->ND > 0) {                                                                         \
+        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
+        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
+        return hipErrorInvalidValue;                                                           \
+    }                                                                                          \
+    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, 8, 2, 1, 1, 2, FULLX, F32C, 0); \
     return hipErrorInvalidValue;
 
 #define MG_COOP_DISPATCH(CALL)                                                                 \
@@ -456,12 +651,12 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds) {
         const bool full = (ops->grid.nx == 64 * sh.PX);                                        \
         const bool f32 = precision == MG_FP32C;                                                \
         if (sh.PX == 4) {                                                                      \
-            if (full) { if (f32) { MG_COOP_SHAPES(4, 8, true, true, CALL) } else { MG_COOP_SHAPES(4, 8, true, false, CALL) } } \
-            else { if (f32) { MG_COOP_SHAPES(4, 8, false, true, CALL) } else { MG_COOP_SHAPES(4, 8, false, false, CALL) } } \
+            if (full) { if (f32) { MG_COOP_SHAPES_X(4, 8, true, true, CALL) } else { MG_COOP_SHAPES_X(4, 8, true, false, CALL) } } \
+            else { if (f32) { MG_COOP_SHAPES_X(4, 8, false, true, CALL) } else { MG_COOP_SHAPES_X(4, 8, false, false, CALL) } } \
         }                                                                                      \
         if (sh.PX == 8) {                                                                      \
-            if (full) { if (f32) { MG_COOP_SHAPES(8, 4, true, true, CALL) } else { MG_COOP_SHAPES(8, 4, true, false, CALL) } } \
-            else { if (f32) { MG_COOP_SHAPES(8, 4, false, true, CALL) } else { MG_COOP_SHAPES(8, 4, false, false, CALL) } } \
+            if (full) { if (f32) { MG_COOP_SHAPES_X(8, 4, true, true, CALL) } else { MG_COOP_SHAPES_X(8, 4, true, false, CALL) } } \
+            else { if (f32) { MG_COOP_SHAPES_X(8, 4, false, true, CALL) } else { MG_COOP_SHAPES_X(8, 4, false, false, CALL) } } \
         }                                                                                      \
         if (sh.PX == 16 && f32) {                                                              \
             if (full) { MG_COOP_SHAPES(16, 2, true, true, CALL) } else { MG_COOP_SHAPES(16, 2, false, true, CALL) } \
@@ -469,18 +664,45 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds) {
         return hipErrorInvalidValue;                                                           \
     }
 
-hipError_t coop_info(const mg_ops* ops, int precision, const void** fn, size_t* lds) {
+// the Euler kernel exists in FP64 for nx <= 512
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
+hipError_t euler_kernel_info(const void** fn, size_t* lds) {
+    if constexpr (F32C || PX > 8) {
+        return hipErrorInvalidValue;
+    } else {
+        constexpr int RH = halo_rows<R0, R1, R2, ND>();
+        *fn = (const void*)euler_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
+        *lds = coop_lds_bytes<PX, NW, RH, ND, double>();
+        return hipSuccess;
+    }
+}
+
+hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, const void** fn,
+                     size_t* lds) {
     CoopShape sh;
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-#define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32) \
-    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32>(fn, lds)
+    if (kind == CoopKind::Euler) {
+        if (precision != MG_FP64) return hipErrorInvalidValue;
+#define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
+    euler_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds)
+        MG_COOP_DISPATCH(MG_CALL_INFO)
+#undef MG_CALL_INFO
+    }
+#define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
+    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds)
     MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
 }
 
 }  // namespace
+
+bool coop_supported(const mg_ops* ops, int precision, CoopKind kind) {
+    const void* fn = nullptr;
+    size_t lds = 0;
+    return coop_info(ops, precision, kind, &fn, &lds) == hipSuccess;
+}
 
 int coop_rows_per_group_member(int nx) {
     CoopShape sh;
@@ -488,7 +710,7 @@ int coop_rows_per_group_member(int nx) {
 }
 
 // Plan: members per path (G), number of resident groups, exchange-area bytes.
-hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan) {
+hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan, CoopKind kind) {
     CoopShape sh;
     plan->stage = 1;
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
@@ -500,7 +722,7 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     const void* fn = nullptr;
     size_t lds = 0;
     plan->stage = 3;
-    hipError_t e = coop_info(ops, precision, &fn, &lds);
+    hipError_t e = coop_info(ops, precision, kind, &fn, &lds);
     if (e != hipSuccess) return e;
     plan->lds = lds;
     int dev = 0, cus = 0, per_cu = 0;
@@ -541,15 +763,27 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     return hipSuccess;
 }
 
+namespace {
+XArea xarea_of(char* xarea, const CoopPlan& plan) {
+    XArea x;
+    x.xh = xarea;
+    x.xn = reinterpret_cast<double*>(xarea + plan.xh_bytes);
+    x.fl = reinterpret_cast<int*>(xarea + plan.xh_bytes + plan.xn_bytes);
+    x.abort_word = x.fl + (size_t)plan.ngroups * plan.G;
+    x.G = plan.G;
+    x.ngroups = plan.ngroups;
+    x.xcd_map = plan.xcd_map;
+    return x;
+}
+}  // namespace
+
 hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
                              int K, const double* u0, int u0_broadcast, double* uT, double tol,
                              int precision, int32_t* stats, int32_t* flags, char* xarea,
                              const CoopPlan& plan, hipStream_t s) {
     const void* fn = nullptr;
     size_t lds = 0;
-    // this kernel reads tables without x-dependent factors
-    if (ops->ND != 0) return hipErrorInvalidValue;
-    hipError_t e = coop_info(ops, precision, &fn, &lds);
+    hipError_t e = coop_info(ops, precision, CoopKind::Expmv, &fn, &lds);
     if (e != hipSuccess) return e;
     CoopArgs a;
     a.tables = tables;
@@ -564,16 +798,43 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
     a.tol = tol;
     a.stats = stats;
     a.flags = flags;
-    a.xh = xarea;
-    a.xn = reinterpret_cast<double*>(xarea + plan.xh_bytes);
-    a.fl = reinterpret_cast<int*>(xarea + plan.xh_bytes + plan.xn_bytes);
-    a.abort_word = a.fl + (size_t)plan.ngroups * plan.G;
-    a.G = plan.G;
-    a.ngroups = plan.ngroups;
-    a.xcd_map = plan.xcd_map;
+    a.xdiag = ops->xdiag_dev;
+    a.x = xarea_of(xarea, plan);
     const int nfl = plan.ngroups * plan.G;
-    hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.fl, nfl,
-                       a.abort_word);
+    hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.x.fl, nfl,
+                       a.x.abort_word);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    void* args[] = {&a};
+    e = hipLaunchCooperativeKernel(fn, dim3((unsigned)(plan.ngroups * plan.G)),
+                                   dim3(plan.threads), args, (unsigned)lds, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_euler_coop(const mg_ops* ops, double* u, int64_t P, const double* dWE, int NE,
+                             double dt, int32_t* flags, char* xarea, const CoopPlan& plan,
+                             hipStream_t s) {
+    const void* fn = nullptr;
+    size_t lds = 0;
+    hipError_t e = coop_info(ops, MG_FP64, CoopKind::Euler, &fn, &lds);
+    if (e != hipSuccess) return e;
+    EulerCoopArgs a;
+    a.basis = ops->basis_dev;
+    a.nx = ops->grid.nx;
+    a.nv = ops->grid.nv;
+    a.nv_pad = ops->nv_pad;
+    a.P = P;
+    a.u = u;
+    a.dWE = dWE;
+    a.NE = NE;
+    a.dt = dt;
+    a.flags = flags;
+    a.xdiag = ops->xdiag_dev;
+    a.x = xarea_of(xarea, plan);
+    const int nfl = plan.ngroups * plan.G;
+    hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.x.fl, nfl,
+                       a.x.abort_word);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     void* args[] = {&a};

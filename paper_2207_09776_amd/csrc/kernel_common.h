@@ -278,6 +278,48 @@ __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
         for (int q = 0; q < PX; ++q) d[r][q] = res[r][q];
 }
 
+// apply_inplace with x-dependent factors: every factor W_t (x) diag(a_t) adds
+// a_t(x) * sum_b W_t[j][b] d(j+b) to row j before it is emitted (a_t at this
+// lane's point q is xa(t, q)).  The W bands follow the V bands in the table row; their
+// coefficients are requested at the start of the row.  Row r is emitted before
+// apply_inplace overwrites d[r - RH], so the rows r - RW .. r + RW read here
+// are still the input (RW <= RH).
+template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, int RW,
+          class T, class Coef, class XA, class Emit>
+__device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
+                                       const T (&bot)[RH][PX], Coef coef, XA xa, int lane, int nx,
+                                       Emit emit) {
+    constexpr int NBM = Bands<R0, R1, R2>::NB;
+    constexpr int WL = 2 * RW + 1;
+    static_assert(RW <= RH, "halo narrower than the x-dependent factors");
+    apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(
+        d, top, bot, coef, lane, nx, [&](int r, T (&y)[PX]) {
+            auto din = [&](int rr, int q) -> T {
+                if (rr < 0) return top[rr + RH][q];
+                if (rr >= RJ) return bot[rr - RJ][q];
+                return d[rr][q];
+            };
+            T w[ND][WL];
+#pragma unroll
+            for (int t = 0; t < ND; ++t)
+#pragma unroll
+                for (int b = 0; b < WL; ++b) w[t][b] = coef(r, NBM + t * WL + b);
+#pragma unroll
+            for (int t = 0; t < ND; ++t) {
+                T z[PX];
+#pragma unroll
+                for (int q = 0; q < PX; ++q) z[q] = w[t][0] * din(r - RW, q);
+#pragma unroll
+                for (int b = 1; b < WL; ++b)
+#pragma unroll
+                    for (int q = 0; q < PX; ++q) z[q] = fma(w[t][b], din(r - RW + b, q), z[q]);
+#pragma unroll
+                for (int q = 0; q < PX; ++q) y[q] = fma(xa(t, q), z[q], y[q]);
+            }
+            emit(r, y);
+        });
+}
+
 // One application of the banded-Kronecker operator in "difference first" form,
 // from d into a separate output.  Because V_q acts along v and Dt along x,
 // V_q (x) Dt^q = (V_q (x) I)(I (x) Dt^q): each row's x differences e1 = Dt d and

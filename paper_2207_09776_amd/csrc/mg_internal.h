@@ -85,6 +85,10 @@ hipError_t launch_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const 
 int resident_rows(int nx, int nv);
 // rows per workgroup of the cooperative kernel for this nx (0: no shape)
 int coop_rows_per_group_member(int nx);
+// cooperative kernels: the Taylor chain and Euler-Maruyama (FP64)
+enum class CoopKind { Expmv, Euler };
+// a cooperative kernel of this kind exists for this operator and precision
+bool coop_supported(const mg_ops* ops, int precision, CoopKind kind = CoopKind::Expmv);
 
 // Cooperative launch plan: G workgroups per path, ngroups resident groups and
 // the exchange area they need (placed after the tables in the workspace).
@@ -93,11 +97,16 @@ struct CoopPlan {
     int stage = 0;   // how far planning got (diagnostics)
     size_t lds = 0, xh_bytes = 0, xn_bytes = 0, fl_bytes = 0, bytes = 0;
 };
-hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan);
+hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan,
+                     CoopKind kind = CoopKind::Expmv);
 hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
                              int K, const double* u0, int u0_broadcast, double* uT, double tol,
                              int precision, int32_t* stats, int32_t* flags, char* xarea,
                              const CoopPlan& plan, hipStream_t s);
+// Euler-Maruyama for grids beyond the register-resident kernel (plan of kind Euler)
+hipError_t launch_euler_coop(const mg_ops* ops, double* u, int64_t P, const double* dWE, int NE,
+                             double dt, int32_t* flags, char* xarea, const CoopPlan& plan,
+                             hipStream_t s);
 
 // host operator build (ops_build.cpp)
 mg_status mg_build_host(const mg_grid* grid, const mg_coeffs* coeffs, int order, mg_ops* ops);

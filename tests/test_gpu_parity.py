@@ -184,20 +184,24 @@ def test_repeat_runs_are_bitwise_identical():
 
 
 # ------------------------------------------------------------------ a7
-@pytest.mark.parametrize("nx,nv,NE", [(24, 24, 256), (100, 100, 256), (32, 32, 2 ** 12)])
-def test_euler_matches_oracle(nx, nv, NE):
+@pytest.mark.parametrize("nx,nv,NE,T,P", [(24, 24, 256, 1.0, 2), (100, 100, 256, 1.0, 2),
+                                          (32, 32, 2 ** 12, 1.0, 2),
+                                          # cooperative Euler (nx > 128); 9 groups are
+                                          # not aligned to the 8 XCDs
+                                          (200, 150, 128, 0.1, 2), (256, 256, 64, 0.02, 9),
+                                          (512, 512, 32, 0.002, 1)])
+def test_euler_matches_oracle(nx, nv, NE, T, P):
     """Step counts respect the explicit stability limit dt <~ dv^2 / a."""
-    say(f"euler {nx}x{nv} NE={NE}")
+    say(f"euler {nx}x{nv} NE={NE} P={P}")
     coeffs = wl.langevin_constant(1.0, 0.5)
     g, B, A, basis, ops = setup_problem(nx, nv, -5.0, 5.0, coeffs, 2)
-    P = 2
-    dW = wl.brownian_increments(8, P, NE * 2)
+    dW = wl.brownian_increments(8, P, NE * 2, T=T)
     dWE = integrals.euler_increments(dW, NE)
     u0 = wl.gaussian_density(nx, nv, -5, 5, -5, 5, 0.25).reshape(-1)
     u = to_dev(np.tile(u0, (P, 1)))
-    flags = mg.euler_step(ops, u, to_dev(dWE), 1.0 / NE)
+    flags = mg.euler_step(ops, u, to_dev(dWE), T / NE)
     torch.cuda.synchronize()
-    want = euler.euler_paths(B, A, u0, dWE, 1.0 / NE)
+    want = euler.euler_paths(B, A, u0, dWE, T / NE)
     for p in range(P):
         assert rel(u[p].cpu().numpy(), want[p]) <= 1e-12
     assert int(flags.abs().sum()) == 0

@@ -45,65 +45,78 @@ def setup_problem(nx, nv, lo, hi, coeffs, order):
 
 
 VAR_CASES = [
-    # (name, nx, nv, order, P, K, Nf, precision, tol)
-    ("var-24x20-m1-f64", 24, 20, 1, 3, 4, 256, "fp64", 1e-10),
-    ("var-24x20-m2-f64", 24, 20, 2, 3, 4, 256, "fp64", 1e-10),
-    ("var-64x64-m2-f64", 64, 64, 2, 2, 8, 512, "fp64", 1e-10),
-    ("var-100x90-m2-f64", 100, 90, 2, 2, 4, 512, "fp64", 1e-10),
-    ("var-128x128-m2-f64", 128, 128, 2, 2, 8, 1024, "fp64", 1e-10),
-    ("var-64x64-m2-f32c", 64, 64, 2, 2, 8, 512, "fp32c", 1e-5),
-    ("var-128x128-m2-f32c", 128, 128, 2, 2, 8, 1024, "fp32c", 1e-5),
+    # (name, nx, nv, order, P, K, Nf, T, precision, tol)
+    ("var-24x20-m1-f64", 24, 20, 1, 3, 4, 256, 1.0, "fp64", 1e-10),
+    ("var-24x20-m2-f64", 24, 20, 2, 3, 4, 256, 1.0, "fp64", 1e-10),
+    ("var-64x64-m2-f64", 64, 64, 2, 2, 8, 512, 1.0, "fp64", 1e-10),
+    ("var-100x90-m2-f64", 100, 90, 2, 2, 4, 512, 1.0, "fp64", 1e-10),
+    ("var-128x128-m2-f64", 128, 128, 2, 2, 8, 1024, 1.0, "fp64", 1e-10),
+    ("var-64x64-m2-f32c", 64, 64, 2, 2, 8, 512, 1.0, "fp32c", 1e-5),
+    ("var-128x128-m2-f32c", 128, 128, 2, 2, 8, 1024, 1.0, "fp32c", 1e-5),
+    # nx > 128: several workgroups per path (cooperative kernel); 200 and 300
+    # leave part of the last lane's points and of the last slab empty
+    ("var-200x150-m1-f64", 200, 150, 1, 2, 2, 256, 0.1, "fp64", 1e-10),
+    ("var-200x150-m2-f64", 200, 150, 2, 2, 2, 256, 0.1, "fp64", 1e-10),
+    ("var-256x256-m2-f32c", 256, 256, 2, 2, 2, 256, 0.05, "fp32c", 1e-5),
+    ("var-300x200-m2-f64", 300, 200, 2, 2, 2, 256, 0.05, "fp64", 1e-10),
+    ("var-300x200-m2-f32c", 300, 200, 2, 2, 2, 256, 0.05, "fp32c", 1e-5),
 ]
 
 
 @pytest.mark.parametrize("case", VAR_CASES, ids=[c[0] for c in VAR_CASES])
 def test_variable_magnus_matches_oracle(case):
-    name, nx, nv, order, P, K, Nf, prec, tol = case
+    name, nx, nv, order, P, K, Nf, T, prec, tol = case
     say(f"variable magnus {name}")
     coeffs = wl.langevin_variable_sigma_beta()
     g, B, A, basis, ops = setup_problem(nx, nv, -5.0, 5.0, coeffs, order)
-    dW = wl.brownian_increments(29, P, Nf)
+    dW = wl.brownian_increments(29, P, Nf, T=T)
     u0 = wl.gaussian_density(nx, nv, -5, 5, -5, 5, 0.25).reshape(-1)
-    coef, _ = mg.iterated_integrals(to_dev(dW), 1.0, K, order)
+    coef, _ = mg.iterated_integrals(to_dev(dW), T, K, order)
     uT, flags, stats = mg.magnus_expmv(ops, coef, to_dev(u0), precision=prec, want_stats=True)
     torch.cuda.synchronize()
     assert int(flags.abs().sum()) == 0, flags.cpu().numpy()
-    want = magnus.iterated_magnus_paths(basis, integrals.path_coefficients(dW, 1.0, K, order), u0)
+    want = magnus.iterated_magnus_paths(basis, integrals.path_coefficients(dW, T, K, order), u0)
     for p in range(P):
         e = rel(uT[p].cpu().numpy(), want[p])
         assert e <= tol, (name, p, e)
 
 
-@pytest.mark.parametrize("nx,nv,NE", [(24, 20, 256), (100, 90, 512)])
-def test_variable_euler_matches_oracle(nx, nv, NE):
-    """Step counts respect the explicit limit dt <~ dv^2 / max g^vv."""
+@pytest.mark.parametrize("nx,nv,NE,T", [(24, 20, 256, 1.0), (100, 90, 512, 1.0),
+                                        (200, 150, 128, 0.1), (300, 200, 96, 0.05)])
+def test_variable_euler_matches_oracle(nx, nv, NE, T):
+    """Step counts respect the explicit limit dt <~ dv^2 / max g^vv; nx > 128
+    runs the cooperative Euler kernel."""
     say(f"variable euler {nx}x{nv} NE={NE}")
     coeffs = wl.langevin_variable_sigma_beta()
     g, B, A, basis, ops = setup_problem(nx, nv, -5.0, 5.0, coeffs, 2)
     P = 2
-    dW = wl.brownian_increments(31, P, NE * 2)
+    dW = wl.brownian_increments(31, P, NE * 2, T=T)
     dWE = integrals.euler_increments(dW, NE)
     u0 = wl.gaussian_density(nx, nv, -5, 5, -5, 5, 0.25).reshape(-1)
     u = to_dev(np.tile(u0, (P, 1)))
-    flags = mg.euler_step(ops, u, to_dev(dWE), 1.0 / NE)
+    flags = mg.euler_step(ops, u, to_dev(dWE), T / NE)
     torch.cuda.synchronize()
-    want = euler.euler_paths(B, A, u0, dWE, 1.0 / NE)
+    want = euler.euler_paths(B, A, u0, dWE, T / NE)
     for p in range(P):
         assert rel(u[p].cpu().numpy(), want[p]) <= 1e-12
     assert int(flags.abs().sum()) == 0
 
 
-def test_variable_above_128_is_reported_unsupported():
-    """The cooperative kernel (nx > 128) takes no x-dependent factors: the call
-    fails with MG_EUNSUPPORTED instead of running."""
-    say("variable 200x150 unsupported")
+def test_variable_above_512_is_reported_unsupported():
+    """x-dependent factors are taken up to nx = 512: a wider grid fails with
+    MG_EUNSUPPORTED (Magnus and Euler) instead of running."""
+    say("variable 600x64 unsupported")
     coeffs = wl.langevin_variable_sigma_beta()
-    arrays = wl.sample_coefficients(coeffs, 200, 150, -5, 5, -5, 5)
-    ops = mg.build_operators(200, 150, -5, 5, -5, 5, arrays, 2)
+    arrays = wl.sample_coefficients(coeffs, 600, 64, -5, 5, -5, 5)
+    ops = mg.build_operators(600, 64, -5, 5, -5, 5, arrays, 2)
     coef = torch.zeros((1, 2, 6), dtype=torch.float64, device=DEV)
-    u0 = torch.zeros(200 * 150, dtype=torch.float64, device=DEV)
+    u0 = torch.zeros(600 * 64, dtype=torch.float64, device=DEV)
     with pytest.raises(mg.MagnusError) as ei:
-        mg.magnus_expmv(ops, coef, u0, ws=torch.empty(1 << 20, dtype=torch.uint8, device=DEV))
+        mg.magnus_expmv(ops, coef, u0, precision="fp32c",
+                        ws=torch.empty(1 << 20, dtype=torch.uint8, device=DEV))
+    assert ei.value.code == mg.MG_EUNSUPPORTED
+    with pytest.raises(mg.MagnusError) as ei:
+        mg.euler_workspace_bytes(ops, 1)
     assert ei.value.code == mg.MG_EUNSUPPORTED
 
 
