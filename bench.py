@@ -321,28 +321,33 @@ def main():
     coef = torch.empty((P, K, 6), dtype=torch.float64, device=dev)
     ps = torch.empty((P, 2), dtype=torch.float64, device=dev)
     uT = torch.empty((P, N), dtype=torch.float64, device=dev)
-    err = torch.empty(P, dtype=torch.float64, device=dev)
     ws = torch.empty(mg.workspace_bytes(ops, P, K), dtype=torch.uint8, device=dev)
     stats = torch.zeros((P, K, 2), dtype=torch.int32, device=dev)
     uref = None
+    R = P                      # paths whose error is formed
     if w.variable:
         # no closed form: the reference is Euler-Maruyama on the fine path
         # itself (Nf steps, finer than every Euler run compared below), formed
-        # once before timing like the closed form is
-        log(f"fine Euler reference: {w.Nf} steps on {P} paths ...")
-        uref = u0.repeat(P, 1).contiguous()
-        flr = mg.euler_step(ops, uref, dW, w.T / w.Nf)
+        # once before timing like the closed form is, on the first R paths
+        R = min(P, w.ref_paths or P)
+        log(f"fine Euler reference: {w.Nf} steps on {R} paths ...")
+        uref = u0.repeat(R, 1).contiguous()
+        flr = mg.euler_step(ops, uref, dW[:R].contiguous(), w.T / w.Nf)
         torch.cuda.synchronize()
         if int((flr != 0).sum()):
             raise RuntimeError("the fine Euler reference is not finite")
+    err = torch.empty(R, dtype=torch.float64, device=dev)
 
     def error_of(u, rows=None, out=None):
-        """Per-path error against the closed form, or the fine reference."""
+        """Per-path error against the closed form, or the fine reference
+        (the first `rows` paths, default R)."""
+        rows = R if rows is None else rows
+        uu = u if rows == u.shape[0] else u[:rows]
         if uref is None:
-            pst = ps if rows is None else ps[:rows].contiguous()
-            return mg.error_vs_exact(ops, u, pathstat=pst, a=w.a, sigma=w.sigma, s0sq=w.s0sq,
+            pst = ps if rows == P else ps[:rows].contiguous()
+            return mg.error_vs_exact(ops, uu, pathstat=pst, a=w.a, sigma=w.sigma, s0sq=w.s0sq,
                                      T=w.T, err=out)
-        return mg.error_vs_exact(ops, u, uref=uref if rows is None else uref[:rows], err=out)
+        return mg.error_vs_exact(ops, uu, uref=uref if rows == R else uref[:rows], err=out)
 
     def step(precision, with_stats=False):
         mg.iterated_integrals(dW, w.T, K, w.order, coef=coef, pathstat=ps)
@@ -405,7 +410,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
                 "traffic": traffic_for(w.name),
-                "kernel": "expmv_resident_kernel",
+                "kernel": "expmv_resident_kernel" if w.n <= 128 else "expmv_coop_kernel",
                 "flops_per_point_term": flops_pt, "taylor_terms": terms,
                 "terms_per_path": terms / P, "substeps_per_path": m64["substeps"] / P,
                 "launch_ms": k_avg_s * 1e3}
@@ -434,7 +439,7 @@ def main():
     # Euler-Maruyama at matched error
     euler = None
     if not args.no_euler:
-        sub = min(64, P)
+        sub = min(64, R)
         target = 1.02 * m64["err_head"]
         chosen = None
         curve = []
@@ -454,23 +459,30 @@ def main():
                 break
         NE = chosen if chosen is not None else (max(curve, key=lambda c: -c[1])[0] if curve
                                                 else 2 ** int(math.log2(w.Nf)))
-        dWE_full = mg.euler_increments(dW, NE)
-        u = u0.repeat(P, 1).contiguous()
-        mg.euler_step(ops, u, dWE_full, w.T / NE)          # warm-up
-        reps = 2
+        # timed on all paths, or on the first PE paths (a batch that fills the
+        # GPU) and scaled to the P paths of the workload
+        PE = min(P, w.euler_time_paths or P)
+        dWs = dW if PE == P else dW[:PE].contiguous()
+        dWE_full = mg.euler_increments(dWs, NE)
+        u = u0.repeat(PE, 1).contiguous()
+        eerr = torch.empty(min(PE, R), dtype=torch.float64, device=dev)
+        reps = 2 if PE == P else 1
+        if PE == P:
+            mg.euler_step(ops, u, dWE_full, w.T / NE)          # warm-up
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            u.copy_(u0.expand(P, N))
-            mg.euler_increments(dW, NE, dWE=dWE_full)
+            u.copy_(u0.expand(PE, N))
+            mg.euler_increments(dWs, NE, dWE=dWE_full)
             mg.euler_step(ops, u, dWE_full, w.T / NE)
-            error_of(u, out=err)
+            error_of(u, rows=min(PE, R), out=eerr)
         e1.record()
         torch.cuda.synchronize()
-        eu_ms = e0.elapsed_time(e1) / reps
-        euler = {"steps": NE, "matched": chosen is not None, "mean_err": float(err.mean()),
+        eu_ms = e0.elapsed_time(e1) / reps * (P / PE)
+        euler = {"steps": NE, "matched": chosen is not None, "mean_err": float(eerr.mean()),
                  "target_err_64_paths": target, "curve_64_paths": curve,
+                 "timed_paths": PE,
                  "paths_per_s": P / (eu_ms / 1e3), "ms_per_batch": eu_ms,
                  "magnus_speedup": (P / (ms_per_step / 1e3)) / (P / (eu_ms / 1e3)),
                  "achieved_TFLOPs": P * NE * N * EULER_FLOPS_PT / (eu_ms / 1e3) / 1e12}
@@ -517,8 +529,8 @@ def main():
                    "coefficients": ({"fx": "-v", "gvv": "(1 + 0.3 sin(pi x/5) exp(-v^2/8))^2",
                                      "sv": "0.5 + 0.2 tanh(v)"} if w.variable
                                     else {"fx": "-v", "gvv": w.a, "sv": w.sigma}),
-                   "error_reference": (f"Euler-Maruyama, {w.Nf} steps" if w.variable
-                                       else "closed form"),
+                   "error_reference": (f"Euler-Maruyama, {w.Nf} steps, first {R} paths"
+                                       if w.variable else "closed form"),
                    "initial": f"N(0,{w.s0sq} I)", "precision": "fp64",
                    "parallelism": "paths across workgroups, one GPU"},
         "mean_err_vs_exact": mean_err,

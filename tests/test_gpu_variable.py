@@ -137,3 +137,51 @@ def test_full_size_var128_sampled_paths():
         c = integrals.path_coefficients(dW[p:p + 1], w.T, w.K, w.order)[0]
         want = magnus.iterated_magnus(basis, c, u0)
         assert rel(uT[p].cpu().numpy(), want) <= 1e-10, p
+
+
+def test_full_size_var512_short_horizon_sampled_paths():
+    """The 512^2 variable-coefficient workload's launch configuration (512
+    paths, one cooperative group per path, FP32C and FP64) over a horizon the
+    oracle can follow (T = 0.004, two Magnus steps); paths 0 and 511 are
+    checked against the oracle one by one."""
+    w = wl.WORKLOADS["var-512-p512-m2-k128"]
+    say(f"variable magnus full-launch short horizon {w.name}")
+    T, K, Nf = 0.004, 2, 64
+    g, B, A, basis, ops = setup_problem(w.n, w.n, w.lo, w.hi, w.coefficients(), w.order)
+    dW = wl.brownian_increments(w.seed, w.paths, Nf, T=T)
+    u0 = wl.gaussian_density(w.n, w.n, w.lo, w.hi, w.lo, w.hi, w.s0sq).reshape(-1)
+    coef, _ = mg.iterated_integrals(to_dev(dW), T, K, w.order)
+    got = {}
+    for prec in ("fp32c", "fp64"):
+        uT, flags, _ = mg.magnus_expmv(ops, coef, to_dev(u0), precision=prec)
+        torch.cuda.synchronize()
+        assert int(flags.abs().sum()) == 0, prec
+        got[prec] = uT[[0, 511]].cpu().numpy()
+    for i, p in enumerate((0, 511)):
+        c = integrals.path_coefficients(dW[p:p + 1], T, K, w.order)[0]
+        want = magnus.iterated_magnus(basis, c, u0)
+        assert rel(got["fp64"][i], want) <= 1e-10, p
+        assert rel(got["fp32c"][i], want) <= 1e-5, p
+
+
+def test_full_size_var512_against_fine_euler():
+    """The 512^2 variable-coefficient workload as the benchmark runs it (512
+    paths, m2, K = 128, FP32C): no path flagged, and on the 16 paths with the
+    fine Euler reference (2^18 steps) the median error is below 2e-3 (the
+    Magnus error at K = 128; the Euler reference itself is tested against the
+    oracle above)."""
+    w = wl.WORKLOADS["var-512-p512-m2-k128"]
+    say(f"variable magnus full {w.name} vs fine Euler")
+    arrays = wl.sample_coefficients(w.coefficients(), w.n, w.n, w.lo, w.hi, w.lo, w.hi)
+    ops = mg.build_operators(w.n, w.n, w.lo, w.hi, w.lo, w.hi, arrays, w.order)
+    dW = to_dev(wl.brownian_increments(w.seed, w.paths, w.Nf))
+    u0 = to_dev(wl.gaussian_density(w.n, w.n, w.lo, w.hi, w.lo, w.hi, w.s0sq).reshape(-1))
+    coef, _ = mg.iterated_integrals(dW, w.T, w.K, w.order)
+    uT, flags, _ = mg.magnus_expmv(ops, coef, u0, precision="fp32c")
+    R = w.ref_paths
+    uref = u0.repeat(R, 1).contiguous()
+    fl = mg.euler_step(ops, uref, dW[:R].contiguous(), w.T / w.Nf)
+    err = mg.error_vs_exact(ops, uT[:R], uref=uref)
+    torch.cuda.synchronize()
+    assert int(flags.abs().sum()) == 0 and int(fl.abs().sum()) == 0
+    assert float(err.median()) <= 2e-3, err.cpu().numpy()

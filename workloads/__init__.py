@@ -99,6 +99,8 @@ class Workload:
     a: float = 1.0              # g^vv (constant case)
     sigma: float = 0.5          # sigma^v (constant case)
     euler_steps: int = 0        # Euler-Maruyama steps of the baseline (0: none)
+    ref_paths: int = 0          # leading paths given the fine Euler reference (0: all)
+    euler_time_paths: int = 0   # paths the Euler baseline is timed on (0: all)
     precision: str = "fp64"     # "fp64" or "fp32c"
     variable: bool = False      # variable-coefficient workload
     extra: Tuple = field(default_factory=tuple)
@@ -122,8 +124,15 @@ WORKLOADS: Dict[str, Workload] = {
                                         2 ** 14, 2, euler_steps=2 ** 14),
     "const-256-p4096-m3-k32-fp32c": Workload("const-256-p4096-m3-k32-fp32c", 256, -5.0, 5.0, 4096,
                                               32, 3, 2 ** 14, 3, precision="fp32c"),
-    "var-512-p512-m2-k64": Workload("var-512-p512-m2-k64", 512, -5.0, 5.0, 512, 64, 2, 2 ** 18, 4,
-                                     variable=True, euler_steps=2 ** 14),
+    # The variable-coefficient workload at 512^2.  K = 128: the order-2
+    # logarithm (its c3 [B,A] term) has an unbounded exponential at K = 64 on
+    # this grid, as in the constant case.  The fine-step Euler reference
+    # (2^18 steps) is formed on the first 16 paths, and the Euler baseline is
+    # timed on 16 paths (one path per group of workgroups that the GPU holds
+    # at once) and scaled to paths/s.
+    "var-512-p512-m2-k128": Workload("var-512-p512-m2-k128", 512, -5.0, 5.0, 512, 128, 2, 2 ** 18,
+                                      4, variable=True, euler_steps=2 ** 14, ref_paths=16,
+                                      euler_time_paths=16),
     # the variable-coefficient workload on a 128^2 grid (the x-dependent
     # operator runs on one workgroup per path up to 128 points per axis)
     "var-128-p512-m2-k64": Workload("var-128-p512-m2-k64", 128, -5.0, 5.0, 512, 64, 2, 2 ** 18, 4,
