@@ -144,7 +144,7 @@ def test_full_size_var512_short_horizon_sampled_paths():
     paths, one cooperative group per path, FP32C and FP64) over a horizon the
     oracle can follow (T = 0.004, two Magnus steps); paths 0 and 511 are
     checked against the oracle one by one."""
-    w = wl.WORKLOADS["var-512-p512-m2-k128"]
+    w = wl.WORKLOADS["var-512-p512-m2-k256"]
     say(f"variable magnus full-launch short horizon {w.name}")
     T, K, Nf = 0.004, 2, 64
     g, B, A, basis, ops = setup_problem(w.n, w.n, w.lo, w.hi, w.coefficients(), w.order)
@@ -166,11 +166,11 @@ def test_full_size_var512_short_horizon_sampled_paths():
 
 def test_full_size_var512_against_fine_euler():
     """The 512^2 variable-coefficient workload as the benchmark runs it (512
-    paths, m2, K = 128, FP32C): no path flagged, and on the 16 paths with the
-    fine Euler reference (2^18 steps) the median error is below 2e-3 (the
-    Magnus error at K = 128; the Euler reference itself is tested against the
-    oracle above)."""
-    w = wl.WORKLOADS["var-512-p512-m2-k128"]
+    paths, m2, K = 256, FP32C): no path flagged, and on the 16 paths with the
+    fine Euler reference (2^18 steps) every error is below 2e-3 (Magnus and
+    the reference differ by about the reference's own time-step error, 3e-4;
+    the Euler kernel itself is tested against the oracle above)."""
+    w = wl.WORKLOADS["var-512-p512-m2-k256"]
     say(f"variable magnus full {w.name} vs fine Euler")
     arrays = wl.sample_coefficients(w.coefficients(), w.n, w.n, w.lo, w.hi, w.lo, w.hi)
     ops = mg.build_operators(w.n, w.n, w.lo, w.hi, w.lo, w.hi, arrays, w.order)
@@ -184,4 +184,4 @@ def test_full_size_var512_against_fine_euler():
     err = mg.error_vs_exact(ops, uT[:R], uref=uref)
     torch.cuda.synchronize()
     assert int(flags.abs().sum()) == 0 and int(fl.abs().sum()) == 0
-    assert float(err.median()) <= 2e-3, err.cpu().numpy()
+    assert float(err.max()) <= 2e-3, err.cpu().numpy()
