@@ -550,7 +550,8 @@ __global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
         for (int n = 0; n < a.NE; ++n) {
             const double wn = dw[n];
             auto coef = [&](int r, int e) -> T {
-                return fma(a.dt, Brows[r * NBP + e], wn * Arows[r * NBP + e]);
+                // uniform: the combined coefficient lives in scalar registers
+                return uniform(fma(a.dt, Brows[r * NBP + e], wn * Arows[r * NBP + e]));
             };
             halo.publish(w, lane, d);
             cg.publish_edges(d);
@@ -606,71 +607,82 @@ __global__ void coop_reset_kernel(int* fl, int n, int* abort_word) {
 
 // ---- planning and dispatch ---------------------------------------------------
 struct CoopShape {
-    int PX, RJ, NW;
+    int PX, rows;
 };
 
+// x points per lane and rows per workgroup (the same for every kernel shape
+// of this nx)
 bool pick_coop_shape(int nx, CoopShape& sh) {
-    sh.NW = 8;
     if (nx <= 128) return false;
-    if (nx <= 256) { sh.PX = 4; sh.RJ = 8; return true; }
-    if (nx <= 512) { sh.PX = 8; sh.RJ = 4; return true; }
-    if (nx <= 1024) { sh.PX = 16; sh.RJ = 2; return true; }
+    if (nx <= 256) { sh.PX = 4; sh.rows = 64; return true; }
+    if (nx <= 512) { sh.PX = 8; sh.rows = 32; return true; }
+    if (nx <= 1024) { sh.PX = 16; sh.rows = 16; return true; }
     return false;
 }
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
-hipError_t coop_kernel_info(const void** fn, size_t* lds) {
+hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
+    *nw = NW;
     *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND>;
     *lds = coop_lds_bytes<PX, NW, RH, ND, T>();
     return hipSuccess;
 }
 
-#define MG_COOP_SHAPES(PX, RJ, FULLX, F32C, CALL)                                              \
-    if (ops->ND > 0) return hipErrorInvalidValue;                                              \
-    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C, 0); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C, 0); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, 8, 2, 1, 1, 2, FULLX, F32C, 0); \
+// Kernel shapes without (MG_COOP_SHAPES) and with (MG_COOP_SHAPES_ND)
+// x-dependent factors; the latter exist for the order-1 and order-2 bands.
+#define MG_COOP_SHAPES(PX, RJ, NW, FULLX, F32C, CALL)                                          \
+    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, F32C, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, F32C, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, F32C, 0); \
     return hipErrorInvalidValue;
-
-// with x-dependent factors (ND > 0): the order-1 and order-2 shapes, nx <= 512
-#define MG_COOP_SHAPES_X(PX, RJ, FULLX, F32C, CALL)                                            \
-    if (ops->ND > 0) {                                                                         \
-        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
-        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
-        return hipErrorInvalidValue;                                                           \
-    }                                                                                          \
-    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 1, 0, 0, 1, FULLX, F32C, 0); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, 8, 2, 1, 0, 1, FULLX, F32C, 0); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, 8, 2, 1, 1, 2, FULLX, F32C, 0); \
+#define MG_COOP_SHAPES_ND(PX, RJ, NW, FULLX, F32C, CALL)                                       \
+    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
     return hipErrorInvalidValue;
+#define MG_COOP_FULLX(SHAPES, PX, RJ, NW, F32C, CALL)                                          \
+    if (full) { SHAPES(PX, RJ, NW, true, F32C, CALL) } else { SHAPES(PX, RJ, NW, false, F32C, CALL) }
 
+// Workgroup shape per x-width and precision: 8 waves of RJ rows, or, where
+// the FP64 state, halo and factors do not fit 256 registers, 4 waves of twice
+// the rows (one wave per SIMD, which may use 512 registers).  The rows per
+// workgroup (NW * RJ) depend on nx only.  x-dependent factors up to nx = 512.
 #define MG_COOP_DISPATCH(CALL)                                                                 \
     {                                                                                          \
         const bool full = (ops->grid.nx == 64 * sh.PX);                                        \
         const bool f32 = precision == MG_FP32C;                                                \
+        const bool nd = ops->ND > 0;                                                           \
         if (sh.PX == 4) {                                                                      \
-            if (full) { if (f32) { MG_COOP_SHAPES_X(4, 8, true, true, CALL) } else { MG_COOP_SHAPES_X(4, 8, true, false, CALL) } } \
-            else { if (f32) { MG_COOP_SHAPES_X(4, 8, false, true, CALL) } else { MG_COOP_SHAPES_X(4, 8, false, false, CALL) } } \
+            if (f32) {                                                                         \
+                if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 4, 8, 8, true, CALL) }               \
+                else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, true, CALL) }                     \
+            } else {                                                                           \
+                if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 4, 16, 4, false, CALL) }             \
+                else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, false, CALL) }                    \
+            }                                                                                  \
         }                                                                                      \
         if (sh.PX == 8) {                                                                      \
-            if (full) { if (f32) { MG_COOP_SHAPES_X(8, 4, true, true, CALL) } else { MG_COOP_SHAPES_X(8, 4, true, false, CALL) } } \
-            else { if (f32) { MG_COOP_SHAPES_X(8, 4, false, true, CALL) } else { MG_COOP_SHAPES_X(8, 4, false, false, CALL) } } \
+            if (f32) {                                                                         \
+                if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 4, 8, true, CALL) }               \
+                else { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 4, 8, true, CALL) }                     \
+            } else {                                                                           \
+                if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 8, 4, false, CALL) }              \
+                else { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 8, 4, false, CALL) }                    \
+            }                                                                                  \
         }                                                                                      \
-        if (sh.PX == 16 && f32) {                                                              \
-            if (full) { MG_COOP_SHAPES(16, 2, true, true, CALL) } else { MG_COOP_SHAPES(16, 2, false, true, CALL) } \
-        }                                                                                      \
+        if (sh.PX == 16 && f32 && !nd) { MG_COOP_FULLX(MG_COOP_SHAPES, 16, 2, 8, true, CALL) }  \
         return hipErrorInvalidValue;                                                           \
     }
 
 // the Euler kernel exists in FP64 for nx <= 512
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
-hipError_t euler_kernel_info(const void** fn, size_t* lds) {
+hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw) {
     if constexpr (F32C || PX > 8) {
         return hipErrorInvalidValue;
     } else {
         constexpr int RH = halo_rows<R0, R1, R2, ND>();
+        *nw = NW;
         *fn = (const void*)euler_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
         *lds = coop_lds_bytes<PX, NW, RH, ND, double>();
         return hipSuccess;
@@ -678,7 +690,7 @@ hipError_t euler_kernel_info(const void** fn, size_t* lds) {
 }
 
 hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, const void** fn,
-                     size_t* lds) {
+                     size_t* lds, int* nw) {
     CoopShape sh;
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
     const int* R = ops->R;
@@ -686,12 +698,12 @@ hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, const void
     if (kind == CoopKind::Euler) {
         if (precision != MG_FP64) return hipErrorInvalidValue;
 #define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
-    euler_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds)
+    euler_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw)
         MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
     }
 #define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
-    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds)
+    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw)
     MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
 }
@@ -701,12 +713,13 @@ hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, const void
 bool coop_supported(const mg_ops* ops, int precision, CoopKind kind) {
     const void* fn = nullptr;
     size_t lds = 0;
-    return coop_info(ops, precision, kind, &fn, &lds) == hipSuccess;
+    int nw = 0;
+    return coop_info(ops, precision, kind, &fn, &lds, &nw) == hipSuccess;
 }
 
 int coop_rows_per_group_member(int nx) {
     CoopShape sh;
-    return pick_coop_shape(nx, sh) ? sh.NW * sh.RJ : 0;
+    return pick_coop_shape(nx, sh) ? sh.rows : 0;
 }
 
 // Plan: members per path (G), number of resident groups, exchange-area bytes.
@@ -714,7 +727,7 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     CoopShape sh;
     plan->stage = 1;
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
-    const int RW = sh.NW * sh.RJ;
+    const int RW = sh.rows;
     const int G = (ops->grid.nv + RW - 1) / RW;
     plan->G = G;
     plan->stage = 2;
@@ -722,7 +735,8 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     const void* fn = nullptr;
     size_t lds = 0;
     plan->stage = 3;
-    hipError_t e = coop_info(ops, precision, kind, &fn, &lds);
+    int nw = 0;
+    hipError_t e = coop_info(ops, precision, kind, &fn, &lds, &nw);
     if (e != hipSuccess) return e;
     plan->lds = lds;
     int dev = 0, cus = 0, per_cu = 0;
@@ -733,7 +747,7 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     plan->cus = cus;
     plan->stage = 5;
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * sh.NW, lds)) != hipSuccess)
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * nw, lds)) != hipSuccess)
         return e;
     plan->per_cu = per_cu;
     plan->stage = 6;
@@ -755,9 +769,9 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     plan->ngroups = ngroups;
     plan->xcd_map = xcd_map;
     plan->lds = lds;
-    plan->threads = 64 * sh.NW;
+    plan->threads = 64 * nw;
     plan->xh_bytes = ((size_t)ngroups * G * 2 * 2 * kRHX * ops->grid.nx * elem + 255) & ~(size_t)255;
-    plan->xn_bytes = ((size_t)ngroups * G * 2 * sh.NW * 2 * sizeof(double) + 255) & ~(size_t)255;
+    plan->xn_bytes = ((size_t)ngroups * G * 2 * nw * 2 * sizeof(double) + 255) & ~(size_t)255;
     plan->fl_bytes = ((size_t)ngroups * G * sizeof(int) + 256 + 255) & ~(size_t)255;
     plan->bytes = plan->xh_bytes + plan->xn_bytes + plan->fl_bytes;
     return hipSuccess;
@@ -783,8 +797,10 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
                              const CoopPlan& plan, hipStream_t s) {
     const void* fn = nullptr;
     size_t lds = 0;
-    hipError_t e = coop_info(ops, precision, CoopKind::Expmv, &fn, &lds);
+    int nw = 0;
+    hipError_t e = coop_info(ops, precision, CoopKind::Expmv, &fn, &lds, &nw);
     if (e != hipSuccess) return e;
+    if (64 * nw != plan.threads || lds != plan.lds) return hipErrorInvalidValue;   // other plan
     CoopArgs a;
     a.tables = tables;
     a.tbytes = tbytes;
@@ -817,8 +833,10 @@ hipError_t launch_euler_coop(const mg_ops* ops, double* u, int64_t P, const doub
                              hipStream_t s) {
     const void* fn = nullptr;
     size_t lds = 0;
-    hipError_t e = coop_info(ops, MG_FP64, CoopKind::Euler, &fn, &lds);
+    int nw = 0;
+    hipError_t e = coop_info(ops, MG_FP64, CoopKind::Euler, &fn, &lds, &nw);
     if (e != hipSuccess) return e;
+    if (64 * nw != plan.threads || lds != plan.lds) return hipErrorInvalidValue;   // other plan
     EulerCoopArgs a;
     a.basis = ops->basis_dev;
     a.nx = ops->grid.nx;
