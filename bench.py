@@ -393,13 +393,49 @@ def main():
         res["substeps"] = int(res["stats"][..., 1].sum())
         return res
 
+    def measure_graph(precision, steps):
+        """The same step captured once in a HIP graph and replayed `steps` times
+        between events.  Grids of the register-resident kernel only (the
+        cooperative kernel's launches are not captured).  The replays must
+        reproduce the eager result bit for bit."""
+        if w.n > 128:
+            return None
+        step(precision)
+        torch.cuda.synchronize()
+        eager = uT.clone()
+        eager_err = err.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step(precision)
+        uT.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(uT, eager) and torch.equal(err, eager_err))
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            g.replay()
+        ev1.record()
+        torch.cuda.synchronize()
+        same = same and bool(torch.equal(uT, eager))
+        return {"ms_per_step": ev0.elapsed_time(ev1) / steps, "replays": steps,
+                "matches_eager": same}
+
     m64 = measure("fp64", args.steps, args.warmup)
-    ms_per_step = m64["ms_per_step"]
+    g64 = measure_graph("fp64", args.steps)
+    eager_ms = m64["ms_per_step"]
+    # the figure of record: graph replays where the step is captured (they
+    # must reproduce the eager result), else the eager steps
+    use_graph = g64 is not None and g64["matches_eager"]
+    ms_per_step = g64["ms_per_step"] if use_graph else eager_ms
     paths_per_s = P / (ms_per_step / 1e3)
     mean_err = m64["mean_err"]
     nflag = m64["flagged"]
-    log(f"FP64: mean Err {mean_err:.4e}, flagged paths {nflag}; {ms_per_step:.3f} ms/step "
-        f"(wall {m64['wall_ms']:.3f}), Taylor kernel {m64['launch_ms']:.3f} ms/launch")
+    log(f"FP64: mean Err {mean_err:.4e}, flagged paths {nflag}; {eager_ms:.3f} ms/step eager "
+        f"(wall {m64['wall_ms']:.3f}), "
+        + (f"{g64['ms_per_step']:.3f} ms/step as graph replays (same result: "
+           f"{g64['matches_eager']}), " if g64 else "")
+        + f"Taylor kernel {m64['launch_ms']:.3f} ms/launch")
 
     # algorithmic work of the dominant kernel (per launch)
     terms = m64["terms"]
@@ -432,7 +468,7 @@ def main():
                  "flagged_paths": m32["flagged"], "terms_per_path": m32["terms"] / P,
                  "substeps_per_path": m32["substeps"] / P,
                  "achieved_TFLOPs": fl32 / (m32["launch_ms"] / 1e3) / 1e12,
-                 "speedup_vs_fp64": ms_per_step / m32["ms_per_step"]}
+                 "speedup_vs_fp64": eager_ms / m32["ms_per_step"]}
         log(f"FP32C: {fp32c['paths_per_s']:.1f} paths/s, Err {m32['mean_err']:.4e} "
             f"(rel. diff {rel:.2e}), {fp32c['terms_per_path']:.0f} terms/path")
 
@@ -484,7 +520,7 @@ def main():
                  "target_err_64_paths": target, "curve_64_paths": curve,
                  "timed_paths": PE,
                  "paths_per_s": P / (eu_ms / 1e3), "ms_per_batch": eu_ms,
-                 "magnus_speedup": (P / (ms_per_step / 1e3)) / (P / (eu_ms / 1e3)),
+                 "magnus_speedup": eu_ms / eager_ms,
                  "achieved_TFLOPs": P * NE * N * EULER_FLOPS_PT / (eu_ms / 1e3) / 1e12}
         if chosen is None and len(curve) >= 2:
             # no power of two up to the fine resolution reaches the target:
@@ -500,7 +536,7 @@ def main():
                 t_star = eu_ms * nstar / NE
                 ext.update({"steps": nstar, "ms_per_batch": t_star,
                             "paths_per_s": P / (t_star / 1e3),
-                            "magnus_speedup": t_star / ms_per_step})
+                            "magnus_speedup": t_star / eager_ms})
             euler["extrapolated"] = ext
         log(f"euler at NE={NE}: {euler['paths_per_s']:.1f} paths/s, Err {euler['mean_err']:.4e}")
 
@@ -533,6 +569,9 @@ def main():
                                        if w.variable else "closed form"),
                    "initial": f"N(0,{w.s0sq} I)", "precision": "fp64",
                    "parallelism": "paths across workgroups, one GPU"},
+        "timing": {"source": "hip graph replays" if use_graph else "eager steps",
+                   "eager_ms_per_step": eager_ms,
+                   "graph": g64},
         "mean_err_vs_exact": mean_err,
         "flagged_paths": nflag,
         "roofline": roofline,

@@ -1,0 +1,57 @@
+"""The hot path captured in a HIP graph (torch.cuda.CUDAGraph over the C ABI
+calls, as the benchmark replays it): every replay, with eager work of the
+program between replays, reproduces the eager result bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2207_09776_amd as mg
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def test_graph_replays_match_eager():
+    print("graph replay 64x64 P=8 K=4", flush=True)
+    sys.stdout.flush()
+    n, P, K, Nf = 64, 8, 4, 256
+    c = wl.langevin_constant(1.0, 0.5)
+    ops = mg.build_operators(n, n, -5, 5, -5, 5, wl.sample_coefficients(c, n, n, -5, 5, -5, 5), 2)
+    u0 = torch.from_numpy(wl.gaussian_density(n, n, -5, 5, -5, 5, 0.25).reshape(-1)).to(DEV)
+    dW = torch.from_numpy(wl.brownian_increments(41, P, Nf)).to(DEV)
+    coef = torch.empty((P, K, 6), dtype=torch.float64, device=DEV)
+    ps = torch.empty((P, 2), dtype=torch.float64, device=DEV)
+    uT = torch.empty((P, n * n), dtype=torch.float64, device=DEV)
+    err = torch.empty(P, dtype=torch.float64, device=DEV)
+    ws = torch.empty(mg.workspace_bytes(ops, P, K), dtype=torch.uint8, device=DEV)
+
+    def step():
+        mg.iterated_integrals(dW, 1.0, K, 2, coef=coef, pathstat=ps)
+        mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws)
+        mg.error_vs_exact(ops, uT, pathstat=ps, a=1.0, sigma=0.5, s0sq=0.25, T=1.0, err=err)
+
+    step()
+    torch.cuda.synchronize()
+    want_u, want_e = uT.clone(), err.clone()
+    assert bool(torch.isfinite(want_u).all())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    other = torch.from_numpy(wl.brownian_increments(43, P, Nf)).to(DEV)
+    for r in range(3):
+        uT.zero_()
+        err.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(uT, want_u), r
+        assert torch.equal(err, want_e), r
+        # eager work between replays: another batch through the same library
+        cf, _ = mg.iterated_integrals(other, 1.0, K, 2)
+        u2, fl, _ = mg.magnus_expmv(ops, cf, u0)
+        torch.cuda.synchronize()
+        assert int(fl.abs().sum()) == 0
