@@ -421,6 +421,15 @@ def main():
         return {"ms_per_step": ev0.elapsed_time(ev1) / steps, "replays": steps,
                 "matches_eager": same}
 
+    # kernel shapes picked by the library's autotuner on this batch (grids of
+    # the register-resident kernel; not timed)
+    tuned = {}
+    if w.n <= 128:
+        mg.iterated_integrals(dW, w.T, K, w.order, coef=coef, pathstat=ps)
+        for prec in ("fp64",) + (() if args.no_fp32c else ("fp32c",)):
+            tuned[prec] = mg.autotune_expmv(ops, coef, u0, precision=prec, uT=uT, ws=ws, reps=2)
+            log(f"autotune {prec}: {tuned[prec]}")
+
     m64 = measure("fp64", args.steps, args.warmup)
     g64 = measure_graph("fp64", args.steps)
     eager_ms = m64["ms_per_step"]
@@ -572,6 +581,7 @@ def main():
         "timing": {"source": "hip graph replays" if use_graph else "eager steps",
                    "eager_ms_per_step": eager_ms,
                    "graph": g64},
+        "autotune": tuned or None,
         "mean_err_vs_exact": mean_err,
         "flagged_paths": nflag,
         "roofline": roofline,

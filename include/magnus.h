@@ -166,6 +166,28 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
                           void* stream);
 
 /* --------------------------------------------------------------------------
+ * mg_autotune_expmv  (kernel shape of the Taylor chain of mg_magnus_expmv)
+ *
+ * Times the workgroup shapes the library holds for this grid (x points per
+ * lane, rows per wave, waves per workgroup; the same rows per workgroup) on
+ * the given batch, `reps` launches each, checks that every shape reproduces
+ * the default shape's uT bit for bit (they apply the same operations in the
+ * same order), and records the fastest in `ops` for `precision`; later
+ * mg_magnus_expmv calls with this ops and precision use it.  Arguments as
+ * for mg_magnus_expmv (stats and flags are not written); uT is overwritten.
+ * Grids of the cooperative kernel have one shape: the call records nothing.
+ * Unlike the other calls it allocates device memory (a copy of uT) and waits
+ * for the stream; do not run it concurrently with other calls that use ops.
+ *   reps   : 1..100.
+ *   report : host buffer for a one-line summary (may be NULL).
+ * Errors: those of mg_magnus_expmv; MG_ESHAPE (P < 1).
+ * ------------------------------------------------------------------------ */
+mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t K,
+                            const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
+                            double tol, void* ws, size_t ws_bytes, int32_t reps, char* report,
+                            size_t report_bytes, void* stream);
+
+/* --------------------------------------------------------------------------
  * mg_magnus_expmv_multi  (the operation of mg_magnus_expmv for several
  *                         independent batches in one call, e.g. groups of
  *                         paths on grids of different sizes)

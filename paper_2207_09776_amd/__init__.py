@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_workspace_bytes", "mg_magnus_expmv", "mg_workspace_bytes_multi",
-           "mg_magnus_expmv_multi", "mg_euler_increments", "mg_euler_workspace_bytes",
+           "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_euler_increments",
+           "mg_euler_workspace_bytes",
            "mg_euler_step",
            "mg_error_vs_exact",
            "mg_last_error", "mg_timing_enable", "mg_timing_read", "mg_timing_reset", "mg_version")
@@ -79,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_euler_workspace_bytes.argtypes = [vp, i64]
     lib.mg_euler_workspace_bytes.restype = sz
     lib.mg_magnus_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, vp, vp, vp]
+    lib.mg_autotune_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, i32,
+                                      ctypes.c_char_p, sz, vp]
     lib.mg_workspace_bytes_multi.argtypes = [ctypes.POINTER(mg_job), i32]
     lib.mg_workspace_bytes_multi.restype = sz
     lib.mg_magnus_expmv_multi.argtypes = [ctypes.POINTER(mg_job), i32, vp, sz, vp]
@@ -210,6 +213,31 @@ def magnus_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float =
         ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
         float(tol), _ptr(ws), ws.numel(), _ptr(stats), _ptr(flags), _stream(stream)))
     return uT, flags, stats
+
+
+def autotune_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float = 0.0,
+                   uT=None, ws=None, reps: int = 3, stream=None) -> str:
+    """mg_autotune_expmv: times the kernel shapes for this grid on the batch and
+    records the fastest in ops for `precision`; returns the library's summary."""
+    import torch
+    _dev_f64(coef, "coef")
+    _dev_f64(u0, "u0")
+    P, K, six = coef.shape
+    N = ops.grid.nx * ops.grid.nv
+    bcast = 1 if u0.dim() == 1 else 0
+    if u0.numel() != (N if bcast else P * N):
+        raise ValueError("u0 has the wrong size")
+    dev = coef.device
+    if uT is None:
+        uT = torch.empty((P, N), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = torch.empty(max(workspace_bytes(ops, P, K, precision), 1), dtype=torch.uint8,
+                         device=dev)
+    buf = ctypes.create_string_buffer(1024)
+    _check(load_library().mg_autotune_expmv(
+        ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
+        float(tol), _ptr(ws), ws.numel(), int(reps), buf, 1024, _stream(stream)))
+    return buf.value.decode()
 
 
 def _addr(t) -> Optional[int]:

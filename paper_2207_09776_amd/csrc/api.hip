@@ -2,6 +2,7 @@
 // Every check happens on the host before anything is enqueued.
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -263,6 +264,119 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
     if (ws_bytes < c.need)
         return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
     return expmv_launch(c, (char*)ws, (hipStream_t)stream, where);
+}
+
+namespace {
+// number of 64-bit words that differ between a and b (bitwise)
+__global__ void count_differences(const unsigned long long* a, const unsigned long long* b,
+                                  size_t n, unsigned long long* count) {
+    unsigned long long c = 0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        c += a[i] != b[i];
+    if (c) atomicAdd(count, c);
+}
+}  // namespace
+
+mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t K,
+                            const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
+                            double tol, void* ws, size_t ws_bytes, int32_t reps, char* report,
+                            size_t report_bytes, void* stream) {
+    g_last_error.clear();
+    const std::string where = "mg_autotune_expmv";
+    if (report && report_bytes) report[0] = 0;
+    ExpmvCall c{ops, coef, P, K, u0, u0_broadcast, uT, precision, tol, nullptr, nullptr};
+    mg_status st = expmv_prepare(c, where);
+    if (st != MG_OK) return st;
+    if (P == 0) return mg_fail(MG_ESHAPE, where + ": need P >= 1");
+    if (reps < 1 || reps > 100) return mg_fail(MG_EINVAL, where + ": reps must be in 1..100");
+    if (!ws) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (ws_bytes < c.need)
+        return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
+    std::string rep;
+    if (c.fam != Family::Resident) {
+        if (report && report_bytes)
+            snprintf(report, report_bytes, "no alternative shapes for this grid");
+        return MG_OK;
+    }
+    int cand[4][3];
+    const int ncand = resident_candidates(ops->grid.nx, ops->grid.nv, cand, 4);
+    hipStream_t s = (hipStream_t)stream;
+    char* tables = (char*)ws;
+    hipError_t e = launch_assemble(ops, coef, P, K, c.tol, precision, tables, s);
+    if (e != hipSuccess) return hip_fail(e, (where + " (assemble)").c_str());
+    const size_t N = (size_t)ops->grid.nx * ops->grid.nv;
+    double* ref = nullptr;
+    unsigned long long* cnt = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    int best = -1;
+    float best_ms = 0.0f;
+    auto cleanup = [&] {
+        if (ref) (void)hipFree(ref);
+        if (cnt) (void)hipFree(cnt);
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    };
+    // the tuning call is not on a hot path: it allocates a reference copy of
+    // uT and synchronises the stream
+    if ((e = hipMalloc((void**)&ref, (size_t)P * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&cnt, sizeof(unsigned long long))) != hipSuccess ||
+        (e = hipEventCreate(&a)) != hipSuccess || (e = hipEventCreate(&b)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, where.c_str());
+    }
+    for (int i = 0; i < ncand && e == hipSuccess; ++i) {
+        // one launch to warm up (and, for the first shape, the reference result)
+        e = launch_expmv_resident(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
+                                  precision, nullptr, nullptr, s, false, cand[i]);
+        if (e != hipSuccess) break;
+        unsigned long long diff = 0;
+        if (i == 0) {
+            e = hipMemcpyAsync(ref, uT, (size_t)P * N * sizeof(double), hipMemcpyDeviceToDevice, s);
+        } else {
+            e = hipMemsetAsync(cnt, 0, sizeof(unsigned long long), s);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(count_differences, dim3(1024), dim3(256), 0, s,
+                                   reinterpret_cast<const unsigned long long*>(uT),
+                                   reinterpret_cast<const unsigned long long*>(ref),
+                                   (size_t)P * N, cnt);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&diff, cnt, sizeof(diff), hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+        }
+        if (e != hipSuccess) break;
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r)
+            e = launch_expmv_resident(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
+                                      precision, nullptr, nullptr, s, false, cand[i]);
+        (void)hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) break;
+        ms /= (float)reps;
+        char line[160];
+        snprintf(line, sizeof line, "%sPX=%d RJ=%d NW=%d: %.3f ms%s", i ? "; " : "", cand[i][0],
+                 cand[i][1], cand[i][2], ms, diff ? " (result differs: excluded)" : "");
+        rep += line;
+        // every candidate computes the same operations per point in the same
+        // order, so the results must agree bit for bit
+        if (diff == 0 && (best < 0 || ms < best_ms)) {
+            best = i;
+            best_ms = ms;
+        }
+    }
+    cleanup();
+    if (e != hipSuccess) return hip_fail(e, where.c_str());
+    int* t = ops->tuned[precision == MG_FP32C ? 1 : 0];
+    t[0] = cand[best][0];
+    t[1] = cand[best][1];
+    t[2] = cand[best][2];
+    rep += "; chosen PX=" + std::to_string(t[0]) + " RJ=" + std::to_string(t[1]) +
+           " NW=" + std::to_string(t[2]);
+    if (report && report_bytes) snprintf(report, report_bytes, "%s", rep.c_str());
+    return MG_OK;
 }
 
 size_t mg_workspace_bytes_multi(const mg_job* jobs, int32_t njobs) {

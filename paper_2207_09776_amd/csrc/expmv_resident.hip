@@ -624,16 +624,50 @@ hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE,
     if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX, 0); \
     return hipErrorInvalidValue;
 
+#define MG_SHAPE_CASE(SPX, SRJ, SNW, CALL)                                                     \
+    if (sh.PX == SPX && sh.RJ == SRJ && sh.NW == SNW) {                                        \
+        if (full) { MG_FOR_SHAPE(SPX, SRJ, SNW, true, CALL) } else { MG_FOR_SHAPE(SPX, SRJ, SNW, false, CALL) } \
+    }
+// the default shapes (pick_shape)
 #define MG_DISPATCH(CALL)                                                                      \
     {                                                                                          \
         const bool full = (nx == 64 * sh.PX);                                                  \
-        if (sh.PX == 1 && sh.NW == 2) { if (full) { MG_FOR_SHAPE(1, 16, 2, true, CALL) } else { MG_FOR_SHAPE(1, 16, 2, false, CALL) } } \
-        if (sh.PX == 1 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(1, 16, 4, true, CALL) } else { MG_FOR_SHAPE(1, 16, 4, false, CALL) } } \
-        if (sh.PX == 1 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(1, 16, 8, true, CALL) } else { MG_FOR_SHAPE(1, 16, 8, false, CALL) } } \
-        if (sh.PX == 2 && sh.NW == 4) { if (full) { MG_FOR_SHAPE(2, 16, 4, true, CALL) } else { MG_FOR_SHAPE(2, 16, 4, false, CALL) } } \
-        if (sh.PX == 2 && sh.NW == 8) { if (full) { MG_FOR_SHAPE(2, 16, 8, true, CALL) } else { MG_FOR_SHAPE(2, 16, 8, false, CALL) } } \
+        MG_SHAPE_CASE(1, 16, 2, CALL)                                                          \
+        MG_SHAPE_CASE(1, 16, 4, CALL)                                                          \
+        MG_SHAPE_CASE(1, 16, 8, CALL)                                                          \
+        MG_SHAPE_CASE(2, 16, 4, CALL)                                                          \
+        MG_SHAPE_CASE(2, 16, 8, CALL)                                                          \
         return hipErrorInvalidValue;                                                           \
     }
+// the default shapes and the alternatives the autotuner may pick (half the
+// rows per wave, twice the waves; the same rows per workgroup)
+#define MG_DISPATCH_TUNED(CALL)                                                                \
+    {                                                                                          \
+        const bool full = (nx == 64 * sh.PX);                                                  \
+        MG_SHAPE_CASE(1, 16, 2, CALL)                                                          \
+        MG_SHAPE_CASE(1, 16, 4, CALL)                                                          \
+        MG_SHAPE_CASE(1, 16, 8, CALL)                                                          \
+        MG_SHAPE_CASE(2, 16, 4, CALL)                                                          \
+        MG_SHAPE_CASE(2, 16, 8, CALL)                                                          \
+        MG_SHAPE_CASE(1, 8, 4, CALL)                                                           \
+        MG_SHAPE_CASE(1, 8, 8, CALL)                                                           \
+        MG_SHAPE_CASE(1, 8, 16, CALL)                                                          \
+        MG_SHAPE_CASE(2, 8, 8, CALL)                                                           \
+        MG_SHAPE_CASE(2, 8, 16, CALL)                                                          \
+        return hipErrorInvalidValue;                                                           \
+    }
+
+// The shape a launch uses: the default, or the one the autotuner recorded in
+// the operator for this precision (same x width and rows per workgroup).
+bool launch_shape(const mg_ops* ops, int precision, Shape& sh) {
+    if (!pick_shape(ops->grid.nx, ops->grid.nv, sh)) return false;
+    const int* t = ops->tuned[precision == MG_FP32C ? 1 : 0];
+    if (t[0] == sh.PX && t[1] * t[2] == sh.RJ * sh.NW) {
+        sh.RJ = t[1];
+        sh.NW = t[2];
+    }
+    return true;
+}
 
 }  // namespace
 
@@ -642,20 +676,37 @@ int resident_rows(int nx, int nv) {
     return pick_shape(nx, nv, sh) ? sh.NW * sh.RJ : 0;
 }
 
+int resident_candidates(int nx, int nv, int (*shapes)[3], int max) {
+    Shape sh;
+    if (!pick_shape(nx, nv, sh) || max < 1) return 0;
+    int n = 0;
+    shapes[n][0] = sh.PX, shapes[n][1] = sh.RJ, shapes[n][2] = sh.NW, ++n;
+    if (n < max && sh.RJ == 16 && sh.NW <= 8) {
+        shapes[n][0] = sh.PX, shapes[n][1] = 8, shapes[n][2] = 2 * sh.NW, ++n;
+    }
+    return n;
+}
+
 hipError_t launch_expmv_resident(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
                                  int K, const double* u0, int u0_broadcast, double* uT, double tol,
                                  int precision, int32_t* stats, int32_t* flags, hipStream_t s,
-                                 bool dry_run) {
+                                 bool dry_run, const int* shape) {
     Shape sh;
-    const int nx = ops->grid.nx, nv = ops->grid.nv;
-    if (!pick_shape(nx, nv, sh)) return hipErrorInvalidValue;
+    const int nx = ops->grid.nx;
+    if (!launch_shape(ops, precision, sh)) return hipErrorInvalidValue;
+    if (shape) {
+        // an explicit candidate (autotuner): same x width and rows per workgroup
+        if (shape[0] != sh.PX || shape[1] * shape[2] != sh.RJ * sh.NW) return hipErrorInvalidValue;
+        sh.RJ = shape[1];
+        sh.NW = shape[2];
+    }
     if (dry_run) return hipSuccess;
     const int* R = ops->R;
     const int qmax = ops->qmax;
 #define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX, ND)                                   \
     run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX, ND>(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, \
                                               tol, precision, stats, flags, s)
-    MG_DISPATCH(MG_CALL_EXPMV)
+    MG_DISPATCH_TUNED(MG_CALL_EXPMV)
 #undef MG_CALL_EXPMV
 }
 

@@ -45,6 +45,9 @@ struct mg_ops {
     std::vector<double> xdiag_host, xstat_host;
     double* xdiag_dev = nullptr;   // xdiag, then xstat, in one allocation
     int device = 0;
+    // register-resident kernel shape (PX, RJ, NW) recorded by the autotuner
+    // per precision (FP64, FP32C); zeros: the default shape
+    int tuned[2][3] = {{0, 0, 0}, {0, 0, 0}};
 };
 
 // Per-(path, step) table of the scaled Magnus logarithm (written by the
@@ -71,10 +74,12 @@ hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int
                            int precision, char* tables, hipStream_t s);
 // Taylor chain over all K steps for paths whose state fits on one workgroup.
 // Returns hipErrorInvalidValue (without launching) if no kernel shape fits.
+// `shape` (PX, RJ, NW) overrides the shape (autotuner candidates), else the
+// default or the autotuner's record in ops.
 hipError_t launch_expmv_resident(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
                                  int K, const double* u0, int u0_broadcast, double* uT, double tol,
                                  int precision, int32_t* stats, int32_t* flags, hipStream_t s,
-                                 bool dry_run);
+                                 bool dry_run, const int* shape = nullptr);
 hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const double* dWE,
                                  int NE, double dt, int32_t* flags, hipStream_t s, bool dry_run);
 hipError_t launch_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const double* pathstat,
@@ -83,6 +88,9 @@ hipError_t launch_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const 
 
 // rows covered by the resident kernel shape for this grid (0: no shape)
 int resident_rows(int nx, int nv);
+// resident kernel shapes the autotuner may time for this grid (the default
+// first); returns their number (<= max)
+int resident_candidates(int nx, int nv, int (*shapes)[3], int max);
 // rows per workgroup of the cooperative kernel for this nx (0: no shape)
 int coop_rows_per_group_member(int nx);
 // cooperative kernels: the Taylor chain and Euler-Maruyama (FP64)

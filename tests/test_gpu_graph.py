@@ -55,3 +55,27 @@ def test_graph_replays_match_eager():
         u2, fl, _ = mg.magnus_expmv(ops, cf, u0)
         torch.cuda.synchronize()
         assert int(fl.abs().sum()) == 0
+
+
+@pytest.mark.parametrize("n,prec", [(128, "fp64"), (128, "fp32c"), (64, "fp64"), (64, "fp32c")])
+def test_autotune_keeps_results(n, prec):
+    """mg_autotune_expmv times the kernel shapes of the grid and records one;
+    results after tuning equal those before bit for bit (every shape applies
+    the same operations in the same order)."""
+    print(f"autotune {n}^2 {prec}", flush=True)
+    P, K, Nf = 32, 4, 256
+    c = wl.langevin_constant(1.0, 0.5)
+    ops = mg.build_operators(n, n, -5, 5, -5, 5, wl.sample_coefficients(c, n, n, -5, 5, -5, 5), 2)
+    u0 = torch.from_numpy(wl.gaussian_density(n, n, -5, 5, -5, 5, 0.25).reshape(-1)).to(DEV)
+    dW = torch.from_numpy(wl.brownian_increments(47, P, Nf)).to(DEV)
+    coef, _ = mg.iterated_integrals(dW, 1.0, K, 2)
+    before, fl, _ = mg.magnus_expmv(ops, coef, u0, precision=prec)
+    torch.cuda.synchronize()
+    before = before.clone()
+    rep = mg.autotune_expmv(ops, coef, u0, precision=prec, reps=2)
+    print(rep, flush=True)
+    assert "chosen" in rep and "differs" not in rep, rep
+    after, fl2, _ = mg.magnus_expmv(ops, coef, u0, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    assert int(fl.abs().sum()) == 0 and int(fl2.abs().sum()) == 0
