@@ -16,9 +16,12 @@ Modules
   euler      Euler-Maruyama scheme, eq. (EulerMaruyama)
   exact      closed-form solution of the constant-coefficient Langevin SPDE
   errors     error norms ME, AME, Err with the kappa window, eq. (meanErr)
+  step_control  uniform step size from the order-2/order-3 distance
+                (Remark "stepSizeControl")
 
 Pins (tests/test_oracle_*.py) tie every function to facts fixed by the paper
 or by mathematics, not to this code.  Functions without such a pin say
 "parity unpinned" in their docstring.
 """
 from . import operators, integrals, expmv, magnus, euler, exact, errors  # noqa: F401
+from . import step_control  # noqa: F401

@@ -1,0 +1,61 @@
+"""Step-size selection by comparing the Magnus orders 2 and 3.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Remark "stepSizeControl": orders 2 and 3 of the iterated scheme stay close for
+step sizes inside the convergence range, so their distance tells whether a
+step size is small enough: accept it when the two results agree within a
+tolerance, else shrink the step by a given factor.  The order-3 logarithm
+contains the order-2 one, and with many trajectories the test may run on a
+sample of them.
+
+Reading used here (uniform steps for a batch): h = T/K with
+K = K0, K0 f, K0 f^2, ... (each K must divide the number of fine increments
+and stay <= Kmax).  For a sample of paths the distance at K is
+
+    gap(K) = max_p ||u3_p - u2_p||_F / ||u3_p||_F,
+
+u2, u3 the terminal values of the iterated scheme of orders 2 and 3 with the
+same K (the same paths, eq. (MagnusFormulas) for the weights).  The first K
+with gap(K) <= tol is selected; if none qualifies the last K tried is
+returned, marked as not accepted.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence, Tuple
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import errors, integrals, magnus
+
+
+def order_gap(basis: Sequence[sp.spmatrix], dW: np.ndarray, T: float, K: int,
+              u0: np.ndarray, nx: int, nv: int) -> np.ndarray:
+    """||u3 - u2||_F / ||u3||_F per sample path at K uniform steps."""
+    c2 = integrals.path_coefficients(dW, T, K, 2)
+    c3 = integrals.path_coefficients(dW, T, K, 3)
+    u2 = magnus.iterated_magnus_paths(basis, c2, u0)
+    u3 = magnus.iterated_magnus_paths(basis, c3, u0)
+    return np.array([errors.relative_error(u3[p].reshape(nv, nx), u2[p].reshape(nv, nx))
+                     for p in range(u2.shape[0])])
+
+
+def select_steps(basis: Sequence[sp.spmatrix], dW: np.ndarray, T: float, u0: np.ndarray,
+                 nx: int, nv: int, K0: int, factor: int, Kmax: int,
+                 tol: float) -> Tuple[int, float, bool, List[Tuple[int, float]]]:
+    """(K, gap(K), accepted, [(K, gap), ...] of every K tried)."""
+    dW = np.atleast_2d(dW)
+    Nf = dW.shape[1]
+    history: List[Tuple[int, float]] = []
+    K = K0
+    while K <= Kmax and Nf % K == 0:
+        g = float(np.max(order_gap(basis, dW, T, K, u0, nx, nv)))
+        history.append((K, g))
+        if g <= tol:
+            return K, g, True, history
+        K *= factor
+    if not history:
+        raise ValueError("K0 must divide the fine increments and not exceed Kmax")
+    K, g = history[-1]
+    return K, g, False, history

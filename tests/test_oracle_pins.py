@@ -383,3 +383,76 @@ def test_brownian_subrange_equals_full_draw():
     full = wl.brownian_increments(3, 10, 64)
     part = wl.brownian_increments(3, 10, 64, first=4, count=3)
     np.testing.assert_array_equal(part, full[4:7])
+
+
+# ------------------------------------------------- Remark "stepSizeControl"
+def _langevin_small(n, sig=None):
+    g = operators.Grid(n, n, -4, 4, -4, 4)
+    c = wl.langevin_constant(1.0, 0.5) if sig is None else wl.Coefficients(
+        fx=lambda x, v: -v, gvv=lambda x, v: 1.0 + 0 * x, sig=sig)
+    B, A = operators.drift_and_noise(g, c)
+    return operators.magnus_basis(B, A), A
+
+
+@pytest.mark.parametrize("case", ["drift_only", "commuting"])
+def test_step_control_accepts_first_step_when_orders_agree(case):
+    """With A = 0 (Remark 'determLangevin') or A = beta I (commuting noise)
+    every commutator vanishes and orders 2 and 3 are the same exact scheme:
+    the order gap is rounding only and the first step size is accepted."""
+    n = 10
+    if case == "drift_only":
+        g = operators.Grid(n, n, -4, 4, -4, 4)
+        B, A = operators.drift_and_noise(g, wl.Coefficients(fx=lambda x, v: -v,
+                                                            gvv=lambda x, v: 1.0 + 0 * x))
+        basis = operators.magnus_basis(B, A)
+    else:
+        basis, A = _langevin_small(n, sig=lambda x, v: 0.6 + 0 * x)
+    dW = wl.brownian_increments(9, 2, 64)
+    u0 = wl.gaussian_density(n, n, -4, 4, -4, 4, 0.25).reshape(-1)
+    from oracle import step_control
+    gap = step_control.order_gap(basis, dW, 1.0, 2, u0, n, n)
+    assert gap.max() <= 1e-12
+    K, g0, ok, hist = step_control.select_steps(basis, dW, 1.0, u0, n, n, 2, 2, 64, 1e-10)
+    assert (K, ok, len(hist)) == (2, True, 1)
+
+
+def test_step_control_gap_shrinks_at_first_order_or_faster():
+    """Non-commuting Langevin noise: the order-2/order-3 distance is the size
+    of the order-3 terms, c4 [[B,A],A] + c5 [[B,A],B] summed over the steps,
+    which falls at least like h (c4 has mean h^2/12 per step, c5 zero mean and
+    size h^(3/2)): every halving of h cuts the sample's largest gap by at
+    least 1.5x, and 16x smaller steps by at least 16x."""
+    n = 12
+    basis, _ = _langevin_small(n)
+    dW = wl.brownian_increments(7, 3, 256)
+    u0 = wl.gaussian_density(n, n, -4, 4, -4, 4, 0.25).reshape(-1)
+    from oracle import step_control
+    g = [step_control.order_gap(basis, dW, 1.0, K, u0, n, n).max() for K in (2, 4, 8, 16, 32)]
+    for a, b in zip(g, g[1:]):
+        assert b <= a / 1.5, g
+    assert g[-1] <= g[0] / 16, g
+
+
+def test_step_control_selection_rule():
+    """The selection walks K0, f K0, ... and stops at the first gap <= tol;
+    without one it returns the last K tried (within Kmax and dividing Nf),
+    not accepted."""
+    n = 12
+    basis, _ = _langevin_small(n)
+    dW = wl.brownian_increments(7, 3, 256)
+    u0 = wl.gaussian_density(n, n, -4, 4, -4, 4, 0.25).reshape(-1)
+    from oracle import step_control
+    gaps = {K: step_control.order_gap(basis, dW, 1.0, K, u0, n, n).max() for K in (2, 4, 8)}
+    tol = 0.5 * (gaps[4] + gaps[8])       # between the gaps at K = 4 and 8
+    K, g, ok, hist = step_control.select_steps(basis, dW, 1.0, u0, n, n, 2, 2, 64, tol)
+    assert (K, ok) == (8, True) and g == gaps[8] and [k for k, _ in hist] == [2, 4, 8]
+    K, g, ok, hist = step_control.select_steps(basis, dW, 1.0, u0, n, n, 2, 2, 8, 1e-12)
+    assert (K, ok) == (8, False) and [k for k, _ in hist] == [2, 4, 8]
+    K, g, ok, hist = step_control.select_steps(basis, dW, 1.0, u0, n, n, 4, 4, 64, 1e-12)
+    assert (K, ok) == (64, False) and [k for k, _ in hist] == [4, 16, 64]
+    # one fine increment per step: the path is linear on every step, c3 = c4 =
+    # c5 = 0, and the two orders coincide (the gap is exactly zero)
+    K, g, ok, hist = step_control.select_steps(basis, dW, 1.0, u0, n, n, 4, 4, 256, 1e-12)
+    assert (K, ok, g) == (256, True, 0.0) and [k for k, _ in hist] == [4, 16, 64, 256]
+    with pytest.raises(ValueError):
+        step_control.select_steps(basis, dW, 1.0, u0, n, n, 3, 2, 64, 1.0)
