@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-euler", action="store_true", help="skip the Euler baseline")
     ap.add_argument("--no-fp32c", action="store_true", help="skip the compensated FP32 run")
+    ap.add_argument("--no-step-control", action="store_true",
+                    help="skip the order-2/order-3 step-size selection report")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (torch copy_ kernel) so "
                          "that profiler byte counters can be scaled against a known size")
@@ -549,6 +551,27 @@ def main():
             euler["extrapolated"] = ext
         log(f"euler at NE={NE}: {euler['paths_per_s']:.1f} paths/s, Err {euler['mean_err']:.4e}")
 
+    # step-size control (orders 2 and 3 compared on a sample of paths): the
+    # uniform K it would choose for a relative order gap of 1e-3, as context
+    # for the workload's K (not part of the timed step)
+    step_control = None
+    if w.order in (2, 3) and not args.no_step_control:
+        try:
+            o2 = ops if w.order == 2 else mg.build_operators(w.n, w.n, w.lo, w.hi, w.lo, w.hi,
+                                                            coeffs, 2)
+            o3 = ops if w.order == 3 else mg.build_operators(w.n, w.n, w.lo, w.hi, w.lo, w.hi,
+                                                            coeffs, 3)
+            Ps = min(16, P)
+            t0 = time.perf_counter()
+            Ksel, gap, acc = mg.select_magnus_steps(o2, o3, dW[:Ps].contiguous(), w.T, u0,
+                                                    K0=4, factor=2, Kmax=w.Nf, tol=1e-3)
+            step_control = {"sample_paths": Ps, "K0": 4, "factor": 2, "tol": 1e-3, "K": Ksel,
+                            "gap": gap, "accepted": acc, "workload_K": K,
+                            "seconds": time.perf_counter() - t0}
+            log(f"step control: K = {Ksel} (gap {gap:.3e}, accepted {acc}); workload K = {K}")
+        except mg.MagnusError as ex:
+            step_control = {"unsupported": str(ex)}
+
     cpu = None
     if not args.no_cpu:
         log("timing the CPU oracle on a sample of paths ...")
@@ -582,6 +605,7 @@ def main():
                    "eager_ms_per_step": eager_ms,
                    "graph": g64},
         "autotune": tuned or None,
+        "step_control": step_control,
         "mean_err_vs_exact": mean_err,
         "flagged_paths": nflag,
         "roofline": roofline,

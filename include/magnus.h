@@ -235,6 +235,34 @@ mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t N
                               void* stream);
 
 /* --------------------------------------------------------------------------
+ * mg_select_magnus_steps  (Remark "stepSizeControl")
+ *
+ * Chooses a uniform number of Magnus steps for a batch by comparing orders 2
+ * and 3 on a sample of paths: for K = K0, K0*factor, K0*factor^2, ... (each
+ * dividing Nf and <= Kmax) it runs both orders over the sample with K steps
+ * and forms gap(K) = max_p ||u3_p - u2_p||_F / ||u3_p||_F; the first K with
+ * gap(K) <= tol is returned with *accepted = 1, else the last K tried with
+ * *accepted = 0.  A flagged or non-finite sample path counts as an infinite
+ * gap.
+ *   ops2, ops3 : operators of orders 2 and 3 on the same grid and
+ *                coefficients.
+ *   dW         : device FP64 [Ps][Nf], the sample paths' fine increments.
+ *   u0         : device FP64 [N], the initial value of every path.
+ *   precision  : MG_FP64 or MG_FP32C (both orders run in it).
+ *   K_out, gap_out, accepted : host outputs.
+ * A set-up call: it allocates its own device buffers and waits for the
+ * stream.
+ * Errors: MG_EINVAL (NULL, orders not 2 and 3, different grids, K0 not
+ * dividing Nf, factor < 2, Kmax < K0, tol <= 0, T <= 0), MG_ESHAPE,
+ * MG_EUNSUPPORTED, MG_EHIP.
+ * ------------------------------------------------------------------------ */
+mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const double* dW,
+                                 int64_t Ps, int64_t Nf, double T, const double* u0, int32_t K0,
+                                 int32_t factor, int32_t Kmax, double tol, int32_t precision,
+                                 int32_t* K_out, double* gap_out, int32_t* accepted,
+                                 void* stream);
+
+/* --------------------------------------------------------------------------
  * mg_euler_step  (eq. (EulerMaruyama))
  *
  * Runs NE Euler-Maruyama steps in place on every path:

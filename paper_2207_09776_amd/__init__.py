@@ -24,7 +24,8 @@ PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_workspace_bytes", "mg_magnus_expmv", "mg_workspace_bytes_multi",
-           "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_euler_increments",
+           "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_select_magnus_steps",
+           "mg_euler_increments",
            "mg_euler_workspace_bytes",
            "mg_euler_step",
            "mg_error_vs_exact",
@@ -80,6 +81,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_euler_workspace_bytes.argtypes = [vp, i64]
     lib.mg_euler_workspace_bytes.restype = sz
     lib.mg_magnus_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, vp, vp, vp]
+    lib.mg_select_magnus_steps.argtypes = [vp, vp, vp, i64, i64, dbl, vp, i32, i32, i32, dbl, i32,
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int32), vp]
     lib.mg_autotune_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, i32,
                                       ctypes.c_char_p, sz, vp]
     lib.mg_workspace_bytes_multi.argtypes = [ctypes.POINTER(mg_job), i32]
@@ -238,6 +243,24 @@ def autotune_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float
         ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
         float(tol), _ptr(ws), ws.numel(), int(reps), buf, 1024, _stream(stream)))
     return buf.value.decode()
+
+
+def select_magnus_steps(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: int,
+                        factor: int = 2, Kmax: int = 1 << 20, tol: float = 1e-3,
+                        precision: str = "fp64", stream=None):
+    """mg_select_magnus_steps: (K, gap, accepted) from the order-2/order-3
+    distance on the sample paths dW [Ps][Nf]."""
+    _dev_f64(dW, "dW")
+    _dev_f64(u0, "u0")
+    Ps, Nf = dW.shape
+    K = ctypes.c_int32(0)
+    gap = ctypes.c_double(0.0)
+    acc = ctypes.c_int32(0)
+    _check(load_library().mg_select_magnus_steps(
+        ops2.handle, ops3.handle, _ptr(dW), Ps, Nf, float(T), _ptr(u0), int(K0), int(factor),
+        int(Kmax), float(tol), PRECISIONS[precision], ctypes.byref(K), ctypes.byref(gap),
+        ctypes.byref(acc), _stream(stream)))
+    return int(K.value), float(gap.value), bool(acc.value)
 
 
 def _addr(t) -> Optional[int]:

@@ -1,9 +1,11 @@
 // C ABI of the library: argument checking, workspace layout, kernel launches.
 // Every check happens on the host before anything is enqueued.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <string>
@@ -376,6 +378,106 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
     rep += "; chosen PX=" + std::to_string(t[0]) + " RJ=" + std::to_string(t[1]) +
            " NW=" + std::to_string(t[2]);
     if (report && report_bytes) snprintf(report, report_bytes, "%s", rep.c_str());
+    return MG_OK;
+}
+
+mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const double* dW,
+                                 int64_t Ps, int64_t Nf, double T, const double* u0, int32_t K0,
+                                 int32_t factor, int32_t Kmax, double tol, int32_t precision,
+                                 int32_t* K_out, double* gap_out, int32_t* accepted,
+                                 void* stream) {
+    g_last_error.clear();
+    const std::string where = "mg_select_magnus_steps";
+    if (!ops2 || !ops3 || !dW || !u0 || !K_out || !gap_out || !accepted)
+        return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (ops2->order != 2 || ops3->order != 3)
+        return mg_fail(MG_EINVAL, where + ": need operators of orders 2 and 3");
+    const mg_grid& g2 = ops2->grid;
+    const mg_grid& g3 = ops3->grid;
+    if (g2.nx != g3.nx || g2.nv != g3.nv || g2.ax != g3.ax || g2.bx != g3.bx ||
+        g2.av != g3.av || g2.bv != g3.bv)
+        return mg_fail(MG_EINVAL, where + ": the two operators are on different grids");
+    if (Ps < 1 || Ps > 0x7fffffff || Nf < 1) return mg_fail(MG_ESHAPE, where + ": bad sizes");
+    if (K0 < 1 || factor < 2 || Kmax < K0 || Nf % K0 != 0)
+        return mg_fail(MG_EINVAL, where + ": need K0 >= 1 dividing Nf, factor >= 2, Kmax >= K0");
+    if (!(tol > 0.0) || !is_finite(T) || !(T > 0.0))
+        return mg_fail(MG_EINVAL, where + ": need tol > 0 and T > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)g2.nx * g2.nv;
+    // set-up call: its own device buffers, sized for the largest K it may try
+    int64_t Kcap = K0;
+    while (Kcap * factor <= Kmax && Nf % (Kcap * factor) == 0) Kcap *= factor;
+    const size_t ws2 = mg_workspace_bytes(ops2, Ps, (int32_t)Kcap, precision);
+    const size_t ws3 = mg_workspace_bytes(ops3, Ps, (int32_t)Kcap, precision);
+    if (ws2 == 0 || ws3 == 0)
+        return mg_fail(MG_EUNSUPPORTED, where + ": no kernel for this grid and precision");
+    const size_t wsb = std::max(ws2, ws3);
+    double *coef = nullptr, *ps = nullptr, *u2 = nullptr, *u3 = nullptr, *err = nullptr;
+    int32_t* fl = nullptr;
+    void* ws = nullptr;
+    auto cleanup = [&] {
+        for (void* q : {(void*)coef, (void*)ps, (void*)u2, (void*)u3, (void*)err, (void*)fl, ws})
+            if (q) (void)hipFree(q);
+    };
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc((void**)&coef, (size_t)Ps * Kcap * 6 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&ps, (size_t)Ps * 2 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&u2, (size_t)Ps * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&u3, (size_t)Ps * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&err, (size_t)Ps * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&fl, (size_t)Ps * 2 * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&ws, wsb)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, where.c_str());
+    }
+    std::vector<double> herr((size_t)Ps);
+    std::vector<int32_t> hfl((size_t)Ps * 2);
+    mg_status st = MG_OK;
+    int32_t K = K0, lastK = 0;
+    double lastgap = 0.0;
+    bool ok = false;
+    while (K <= Kmax && Nf % K == 0) {
+        // the order-3 weights (their first four are the order-2 ones)
+        if ((st = mg_iterated_integrals(dW, Ps, Nf, T, K, 3, coef, ps, stream)) != MG_OK) break;
+        if ((st = mg_magnus_expmv(ops2, coef, Ps, K, u0, 1, u2, precision, 0.0, ws, wsb, nullptr,
+                                  fl, stream)) != MG_OK)
+            break;
+        if ((st = mg_magnus_expmv(ops3, coef, Ps, K, u0, 1, u3, precision, 0.0, ws, wsb, nullptr,
+                                  fl + Ps, stream)) != MG_OK)
+            break;
+        if ((st = mg_error_vs_exact(&g2, nullptr, nullptr, u2, u3, Ps, 0, err, stream)) != MG_OK)
+            break;
+        if ((e = hipMemcpyAsync(herr.data(), err, (size_t)Ps * sizeof(double),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(hfl.data(), fl, (size_t)Ps * 2 * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess) {
+            st = hip_fail(e, where.c_str());
+            break;
+        }
+        // the largest relative distance over the sample; a flagged or
+        // non-finite path counts as an infinite distance
+        double gap = 0.0;
+        for (int64_t p = 0; p < Ps; ++p) {
+            const double v = (hfl[p] || hfl[Ps + p] || !std::isfinite(herr[p]))
+                                 ? std::numeric_limits<double>::infinity()
+                                 : herr[p];
+            gap = std::max(gap, v);
+        }
+        lastK = K;
+        lastgap = gap;
+        if (gap <= tol) {
+            ok = true;
+            break;
+        }
+        if ((int64_t)K * factor > 0x7fffffff) break;
+        K *= factor;
+    }
+    cleanup();
+    if (st != MG_OK) return st;
+    *K_out = lastK;
+    *gap_out = lastgap;
+    *accepted = ok ? 1 : 0;
     return MG_OK;
 }
 
