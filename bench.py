@@ -192,6 +192,16 @@ def run_mixed(args, w):
     for g in groups:
         total_ws += (mg.workspace_bytes(g["ops"], g["P"], g["K"], prec) + 255) // 256 * 256
     ws = torch.empty(total_ws, dtype=torch.uint8, device=dev)
+    # kernel shapes of the groups on the register-resident kernel, by the
+    # library's autotuner (not timed)
+    tuned = {}
+    for g in groups:
+        if g["n"] <= 128:
+            mg.iterated_integrals(g["dW"], w.T, g["K"], w.order, coef=g["coef"], pathstat=g["ps"])
+            key = str(g["n"]) + "^2"
+            tuned[key] = mg.autotune_expmv(g["ops"], g["coef"], g["u0"], precision=prec,
+                                           uT=g["uT"], reps=2)
+            log(f"autotune {key}: {tuned[key]}")
     out = step(with_stats=True)
     for _ in range(max(0, args.warmup - 1)):
         step()
@@ -209,7 +219,27 @@ def run_mixed(args, w):
         step()
     ev1.record()
     torch.cuda.synchronize()
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    eager_ms = ev0.elapsed_time(ev1) / args.steps
+    # the same step captured in one HIP graph (all groups' launches) and
+    # replayed; the replays must reproduce the eager results bit for bit
+    want = [g["uT"].clone() for g in groups]
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        step()
+    for g in groups:
+        g["uT"].zero_()
+    gr.replay()
+    torch.cuda.synchronize()
+    same = all(bool(torch.equal(g["uT"], x)) for g, x in zip(groups, want))
+    ev0.record()
+    for _ in range(args.steps):
+        gr.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    same = same and all(bool(torch.equal(g["uT"], x)) for g, x in zip(groups, want))
+    ms_per_step = graph_ms if same else eager_ms
+    log(f"step: {eager_ms:.1f} ms eager, {graph_ms:.1f} ms as graph replays (same result: {same})")
     total_paths = sum(g["P"] for g in groups)
     # per-group Taylor kernel time: each group's call alone, timed by the library
     for g, pg in zip(groups, per_group):
@@ -270,6 +300,11 @@ def run_mixed(args, w):
         "vs_baseline": None,
         "dtype": "f32" if prec == "fp32c" else "f64",
         "data": "synthetic",
+        "timing": {"source": "hip graph replays" if same else "eager steps",
+                   "eager_ms_per_step": eager_ms,
+                   "graph": {"ms_per_step": graph_ms, "replays": args.steps,
+                             "matches_eager": same}},
+        "autotune": tuned or None,
         "config": {"workload": w.name, "groups": [[n, P, K] for (n, P, K, _) in w.extra],
                    "domain": [w.lo, w.hi], "order": w.order, "fine_increments": w.Nf, "T": w.T,
                    "coefficients": {"fx": "-v", "gvv": w.a, "sv": w.sigma},
@@ -397,11 +432,8 @@ def main():
 
     def measure_graph(precision, steps):
         """The same step captured once in a HIP graph and replayed `steps` times
-        between events.  Grids of the register-resident kernel only (the
-        cooperative kernel's launches are not captured).  The replays must
-        reproduce the eager result bit for bit."""
-        if w.n > 128:
-            return None
+        between events (cooperative launches are captured too).  The replays
+        must reproduce the eager result bit for bit."""
         step(precision)
         torch.cuda.synchronize()
         eager = uT.clone()

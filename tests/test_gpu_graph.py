@@ -79,3 +79,51 @@ def test_autotune_keeps_results(n, prec):
     torch.cuda.synchronize()
     assert torch.equal(before, after)
     assert int(fl.abs().sum()) == 0 and int(fl2.abs().sum()) == 0
+
+
+def test_graph_replays_cooperative_and_multi_job():
+    """Cooperative launches (256^2, FP32C) and a multi-job call (a resident
+    and a cooperative batch) captured in one graph: every replay, with eager
+    work between replays, equals the eager result bit for bit."""
+    print("graph replay cooperative + multi-job", flush=True)
+    c = wl.langevin_constant(1.0, 0.5)
+    batches = []
+    for (n, P, K, T) in ((256, 8, 2, 0.05), (64, 16, 4, 1.0)):
+        ops = mg.build_operators(n, n, -5, 5, -5, 5, wl.sample_coefficients(c, n, n, -5, 5, -5, 5),
+                                 2)
+        u0 = torch.from_numpy(wl.gaussian_density(n, n, -5, 5, -5, 5, 0.25).reshape(-1)).to(DEV)
+        dW = torch.from_numpy(wl.brownian_increments(51, P, 256, T=T)).to(DEV)
+        coef, _ = mg.iterated_integrals(dW, T, K, 2)
+        uT = torch.empty((P, n * n), dtype=torch.float64, device=DEV)
+        batches.append(dict(ops=ops, coef=coef, u0=u0, uT=uT, precision="fp32c"))
+    b0 = batches[0]
+    ws0 = torch.empty(mg.workspace_bytes(b0["ops"], 8, 2, "fp32c"), dtype=torch.uint8, device=DEV)
+    uT_m = [torch.empty_like(b["uT"]) for b in batches]
+    jobs = [dict(b, uT=u) for b, u in zip(batches, uT_m)]
+    # the multi-job workspace: each job's slice rounded up to 256 bytes
+    need = sum((mg.workspace_bytes(j["ops"], j["coef"].shape[0], j["coef"].shape[1], "fp32c")
+                + 255) // 256 * 256 for j in jobs)
+    wsm = torch.empty(need, dtype=torch.uint8, device=DEV)
+
+    def step():
+        mg.magnus_expmv(b0["ops"], b0["coef"], b0["u0"], precision="fp32c", uT=b0["uT"], ws=ws0)
+        mg.magnus_expmv_multi(jobs, ws=wsm)
+
+    step()
+    torch.cuda.synchronize()
+    want = [b0["uT"].clone()] + [u.clone() for u in uT_m]
+    assert all(bool(torch.isfinite(x).all()) for x in want)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for r in range(3):
+        for x in [b0["uT"]] + uT_m:
+            x.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip([b0["uT"]] + uT_m, want):
+            assert torch.equal(x, y), r
+        # eager work between replays
+        u2, fl, _ = mg.magnus_expmv(b0["ops"], b0["coef"], b0["u0"], precision="fp32c")
+        torch.cuda.synchronize()
+        assert int(fl.abs().sum()) == 0
