@@ -155,15 +155,19 @@ struct CoopGroup {
             g = b % x.G;
             grp = b / x.G;
         }
+        // this group's slices of the exchange area (offsets within them fit
+        // 32 bits: G <= 64 members)
+        xh_g = reinterpret_cast<T*>(x.xh) + (size_t)grp * x.G * 2 * 2 * kRHX * nx;
+        xn_g = x.xn + (size_t)grp * x.G * 2 * NW * 2;
     }
+    T* xh_g;
+    double* xn_g;
     __device__ __forceinline__ T* xh_row(int member, int par, int side, int s) const {
-        return reinterpret_cast<T*>(x.xh) +
-               ((((size_t)grp * x.G + member) * 2 + par) * 2 + side) * (size_t)kRHX * nx +
-               (size_t)s * nx;
+        return xh_g + (((member * 2 + par) * 2 + side) * kRHX + s) * nx;
     }
     // per member and parity: NW pairs (one per wave) of norms
     __device__ __forceinline__ double* xn_at(int member, int par, int wave) const {
-        return x.xn + ((((size_t)grp * x.G + member) * 2 + par) * NW + wave) * 2;
+        return xn_g + ((member * 2 + par) * NW + wave) * 2;
     }
     // edge rows of d for the neighbouring slabs (parity of the coming sync)
     __device__ __forceinline__ void publish_edges(const T (&d)[RJ][PX]) const {
