@@ -163,7 +163,11 @@ struct CoopGroup {
     T* xh_g;
     double* xn_g;
     __device__ __forceinline__ T* xh_row(int member, int par, int side, int s) const {
-        return xh_g + (((member * 2 + par) * 2 + side) * kRHX + s) * nx;
+        return xh_g + (size_t)(unsigned)((((member * 2 + par) * 2 + side) * kRHX + s) * nx);
+    }
+    // this lane's first point in that row (its PX points follow)
+    __device__ __forceinline__ T* xh_lane(int member, int par, int side, int s) const {
+        return xh_row(member, par, side, s) + (unsigned)(lane * PX);
     }
     // per member and parity: NW pairs (one per wave) of norms
     __device__ __forceinline__ double* xn_at(int member, int par, int wave) const {
@@ -178,7 +182,7 @@ struct CoopGroup {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
-                    if (i < nx) xstore(xh_row(g, par, 0, s) + i, d[s][q]);
+                    if (i < nx) xstore(xh_lane(g, par, 0, s) + q, d[s][q]);
                 }
         }
         if (w == NW - 1 && g + 1 < x.G) {
@@ -187,7 +191,7 @@ struct CoopGroup {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
-                    if (i < nx) xstore(xh_row(g, par, 1, s) + i, d[RJ - RH + s][q]);
+                    if (i < nx) xstore(xh_lane(g, par, 1, s) + q, d[RJ - RH + s][q]);
                 }
         }
     }
@@ -238,7 +242,7 @@ struct CoopGroup {
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
                     T v = T(0);
-                    if (g > 0 && i < nx) v = xload(xh_row(g - 1, par, 1, s) + i);
+                    if (g > 0 && i < nx) v = xload(xh_lane(g - 1, par, 1, s) + q);
                     top[s][q] = v;
                 }
         }
@@ -249,7 +253,7 @@ struct CoopGroup {
             for (int q = 0; q < PX; ++q) {
                 const int i = lane * PX + q;
                 T v = T(0);
-                if (last && g + 1 < x.G && i < nx) v = xload(xh_row(g + 1, par, 0, s) + i);
+                if (last && g + 1 < x.G && i < nx) v = xload(xh_lane(g + 1, par, 0, s) + q);
                 bot[s][q] = last ? v : bot[s][q];
             }
     }
