@@ -317,6 +317,77 @@ def run_mixed(args, w):
     print(json.dumps(out))
 
 
+def paper_sweep(args):
+    """Constant-coefficient experiments of Section 3 ("comparison of Magnus
+    and Euler" for d = 100, 200, 300) with the paper's parameters: a = 1.1,
+    sigma = 1/sqrt(10), [-4, 4]^2, Gaussian initial datum exp(-(xi^2+eta^2)/2)
+    (relative errors do not depend on its scale), M = 100 paths, Lebesgue
+    discretisation 1e-4 (Nf = 10^4 for T = 1), Euler with steps 1e-3 and 1e-4,
+    orders 2 and 3 with the step sizes the paper uses per d, errors Err^{d,4}
+    against the closed form.  Paths are synthetic (seed 11), not the paper's;
+    the error magnitudes and ratios are what compares, times are this GPU's."""
+    import torch
+    import paper_2207_09776_amd as mg
+    import workloads as wl
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    a, sigma, lo, hi, T, M, Nf, kappa = 1.1, 1.0 / math.sqrt(10.0), -4.0, 4.0, 1.0, 100, 10 ** 4, 4
+    steps = {100: 0.1, 200: 0.05, 300: 0.025}
+    coeffs = wl.langevin_constant(a, sigma)
+    dW = torch.from_numpy(wl.brownian_increments(11, M, Nf, T)).to(dev)
+    rows = []
+
+    def timed(fn):
+        fn()                                        # warm-up (also the result)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    for d, h in steps.items():
+        K = int(round(T / h))
+        arrays = wl.sample_coefficients(coeffs, d, d, lo, hi, lo, hi)
+        u0 = torch.from_numpy(wl.gaussian_density(d, d, lo, hi, lo, hi, 1.0).reshape(-1)).to(dev)
+        _, ps = mg.iterated_integrals(dW, T, K, 2)
+        res = {"d": d}
+        for order in (2, 3):
+            ops = mg.build_operators(d, d, lo, hi, lo, hi, arrays, order)
+            coef, _ = mg.iterated_integrals(dW, T, K, order)
+            ws = torch.empty(mg.workspace_bytes(ops, M, K), dtype=torch.uint8, device=dev)
+            uT = torch.empty((M, d * d), dtype=torch.float64, device=dev)
+            ms = timed(lambda: mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws))
+            err = mg.error_vs_exact(ops, uT, pathstat=ps, a=a, sigma=sigma, s0sq=1.0, T=T,
+                                    kappa=kappa)
+            res[f"M{order}, {h}"] = {"err_pct": 100 * float(err.mean()), "ms_per_path": ms / M}
+            log(f"d={d} M{order} h={h}: Err {100 * float(err.mean()):.4f} %, {ms / M:.3f} ms/path")
+        ops = mg.build_operators(d, d, lo, hi, lo, hi, arrays, 2)
+        for dt in (1e-3, 1e-4):
+            NE = int(round(T / dt))
+            dWE = mg.euler_increments(dW, NE)
+            u = torch.empty((M, d * d), dtype=torch.float64, device=dev)
+            ws = mg.euler_workspace_bytes(ops, M)
+            wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev) if ws else None
+            flags = {}
+
+            def run():
+                u.copy_(u0.expand(M, d * d))
+                flags["f"] = mg.euler_step(ops, u, dWE, dt, ws=wsb)
+            ms = timed(run)
+            err = mg.error_vs_exact(ops, u, pathstat=ps, a=a, sigma=sigma, s0sq=1.0, T=T,
+                                    kappa=kappa)
+            bad = int((flags["f"] != 0).sum())
+            e = float("inf") if bad else 100 * float(err.mean())
+            res[f"E, {dt:g}"] = {"err_pct": e, "ms_per_path": ms / M, "flagged_paths": bad}
+            log(f"d={d} Euler dt={dt:g}: Err {e:.4f} %, {ms / M:.3f} ms/path")
+        rows.append(res)
+    print(json.dumps({"experiment": "constant-coefficient comparison, Section 3 (paper parameters)",
+                      "paths": M, "fine_increments": Nf, "kappa": kappa, "a": a, "sigma": sigma,
+                      "domain": [lo, hi], "seed": 11, "results": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +402,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (torch copy_ kernel) so "
                          "that profiler byte counters can be scaled against a known size")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="run the paper's constant-coefficient comparison (d = 100, 200, 300) "
+                         "instead of the benchmark line")
     args = ap.parse_args()
+    if args.paper_sweep:
+        return paper_sweep(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only: each path is independent "
                                    "and a multi-GPU run would shard paths (see DESIGN.md); "
