@@ -615,24 +615,24 @@ __global__ void coop_reset_kernel(int* fl, int n, int* abort_word) {
 
 // ---- planning and dispatch ---------------------------------------------------
 struct CoopShape {
-    int PX, rows;
+    int PX;
 };
 
-// x points per lane and rows per workgroup (the same for every kernel shape
-// of this nx)
+// x points per lane
 bool pick_coop_shape(int nx, CoopShape& sh) {
     if (nx <= 128) return false;
-    if (nx <= 256) { sh.PX = 4; sh.rows = 64; return true; }
-    if (nx <= 512) { sh.PX = 8; sh.rows = 32; return true; }
-    if (nx <= 1024) { sh.PX = 16; sh.rows = 16; return true; }
+    if (nx <= 256) { sh.PX = 4; return true; }
+    if (nx <= 512) { sh.PX = 8; return true; }
+    if (nx <= 1024) { sh.PX = 16; return true; }
     return false;
 }
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
-hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw) {
+hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     *nw = NW;
+    *rows = NW * RJ;
     *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND>;
     *lds = coop_lds_bytes<PX, NW, RH, ND, T>();
     return hipSuccess;
@@ -685,12 +685,13 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw) {
 
 // the Euler kernel exists in FP64 for nx <= 512
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
-hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw) {
+hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     if constexpr (F32C || PX > 8) {
         return hipErrorInvalidValue;
     } else {
         constexpr int RH = halo_rows<R0, R1, R2, ND>();
         *nw = NW;
+        *rows = NW * RJ;
         *fn = (const void*)euler_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
         *lds = coop_lds_bytes<PX, NW, RH, ND, double>();
         return hipSuccess;
@@ -698,7 +699,7 @@ hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw) {
 }
 
 hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, const void** fn,
-                     size_t* lds, int* nw) {
+                     size_t* lds, int* nw, int* rows) {
     CoopShape sh;
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
     const int* R = ops->R;
@@ -706,46 +707,46 @@ hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, const void
     if (kind == CoopKind::Euler) {
         if (precision != MG_FP64) return hipErrorInvalidValue;
 #define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
-    euler_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw)
+    euler_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw, rows)
         MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
     }
 #define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
-    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw)
+    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw, rows)
     MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
 }
 
 }  // namespace
 
+int coop_rows_max(int nx) {
+    CoopShape sh;
+    if (!pick_coop_shape(nx, sh)) return 0;
+    // the most rows per workgroup of any shape instantiated for this x width
+    return sh.PX == 4 ? 64 : sh.PX == 8 ? 32 : 16;
+}
+
 bool coop_supported(const mg_ops* ops, int precision, CoopKind kind) {
     const void* fn = nullptr;
     size_t lds = 0;
-    int nw = 0;
-    return coop_info(ops, precision, kind, &fn, &lds, &nw) == hipSuccess;
-}
-
-int coop_rows_per_group_member(int nx) {
-    CoopShape sh;
-    return pick_coop_shape(nx, sh) ? sh.rows : 0;
+    int nw = 0, rows = 0;
+    return coop_info(ops, precision, kind, &fn, &lds, &nw, &rows) == hipSuccess;
 }
 
 // Plan: members per path (G), number of resident groups, exchange-area bytes.
 hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan, CoopKind kind) {
-    CoopShape sh;
+    const void* fn = nullptr;
+    size_t lds = 0;
+    int nw = 0, rows = 0;
     plan->stage = 1;
-    if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
-    const int RW = sh.rows;
-    const int G = (ops->grid.nv + RW - 1) / RW;
+    hipError_t e = coop_info(ops, precision, kind, &fn, &lds, &nw, &rows);
+    if (e != hipSuccess) return e;
+    // G workgroups of `rows` rows hold a path
+    const int G = (ops->grid.nv + rows - 1) / rows;
     plan->G = G;
     plan->stage = 2;
     if (G < 1 || G > 64) return hipErrorInvalidValue;
-    const void* fn = nullptr;
-    size_t lds = 0;
     plan->stage = 3;
-    int nw = 0;
-    hipError_t e = coop_info(ops, precision, kind, &fn, &lds, &nw);
-    if (e != hipSuccess) return e;
     plan->lds = lds;
     int dev = 0, cus = 0, per_cu = 0;
     plan->stage = 4;
@@ -805,8 +806,8 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
                              const CoopPlan& plan, hipStream_t s) {
     const void* fn = nullptr;
     size_t lds = 0;
-    int nw = 0;
-    hipError_t e = coop_info(ops, precision, CoopKind::Expmv, &fn, &lds, &nw);
+    int nw = 0, rows = 0;
+    hipError_t e = coop_info(ops, precision, CoopKind::Expmv, &fn, &lds, &nw, &rows);
     if (e != hipSuccess) return e;
     if (64 * nw != plan.threads || lds != plan.lds) return hipErrorInvalidValue;   // other plan
     CoopArgs a;
@@ -841,8 +842,8 @@ hipError_t launch_euler_coop(const mg_ops* ops, double* u, int64_t P, const doub
                              hipStream_t s) {
     const void* fn = nullptr;
     size_t lds = 0;
-    int nw = 0;
-    hipError_t e = coop_info(ops, MG_FP64, CoopKind::Euler, &fn, &lds, &nw);
+    int nw = 0, rows = 0;
+    hipError_t e = coop_info(ops, MG_FP64, CoopKind::Euler, &fn, &lds, &nw, &rows);
     if (e != hipSuccess) return e;
     if (64 * nw != plan.threads || lds != plan.lds) return hipErrorInvalidValue;   // other plan
     EulerCoopArgs a;

@@ -91,8 +91,9 @@ int resident_rows(int nx, int nv);
 // resident kernel shapes the autotuner may time for this grid (the default
 // first); returns their number (<= max)
 int resident_candidates(int nx, int nv, int (*shapes)[3], int max);
-// rows per workgroup of the cooperative kernel for this nx (0: no shape)
-int coop_rows_per_group_member(int nx);
+// the most rows per workgroup any cooperative kernel shape for this nx uses
+// (operator tables are padded to a multiple of it; 0: no shape)
+int coop_rows_max(int nx);
 // cooperative kernels: the Taylor chain and Euler-Maruyama (FP64)
 enum class CoopKind { Expmv, Euler };
 // a cooperative kernel of this kind exists for this operator and precision

@@ -423,7 +423,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     // table rows are padded to the rows the kernel shape covers
     int rows = resident_rows(nx, nv);
     if (rows == 0) {
-        const int rw = coop_rows_per_group_member(nx);
+        const int rw = coop_rows_max(nx);
         if (rw > 0) rows = (nv + rw - 1) / rw * rw;
     }
     ops->nv_pad = std::max(nv, rows);
