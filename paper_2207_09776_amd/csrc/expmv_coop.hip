@@ -654,8 +654,11 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
 
 // Workgroup shape per x-width and precision: 8 waves of RJ rows, or, where
 // the FP64 state, halo and factors do not fit 256 registers, 4 waves of twice
-// the rows (one wave per SIMD, which may use 512 registers).  The rows per
-// workgroup (NW * RJ) depend on nx only.  x-dependent factors up to nx = 512.
+// the rows (one wave per SIMD, which may use 512 registers).  At nx > 512
+// (FP32C only) 4 waves of 6 rows: 24 rows per workgroup, so 43 members hold a
+// 1024-row path where 16-row workgroups need 64, and the exchange, which grows
+// with the member count, costs less.  The rows per workgroup (NW * RJ) depend
+// on nx only.  x-dependent factors up to nx = 512.
 #define MG_COOP_DISPATCH(CALL)                                                                 \
     {                                                                                          \
         const bool full = (ops->grid.nx == 64 * sh.PX);                                        \
@@ -679,7 +682,7 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 8, 4, false, CALL) }                    \
             }                                                                                  \
         }                                                                                      \
-        if (sh.PX == 16 && f32 && !nd) { MG_COOP_FULLX(MG_COOP_SHAPES, 16, 2, 8, true, CALL) }  \
+        if (sh.PX == 16 && f32 && !nd) { MG_COOP_FULLX(MG_COOP_SHAPES, 16, 6, 4, true, CALL) }  \
         return hipErrorInvalidValue;                                                           \
     }
 
@@ -723,7 +726,7 @@ int coop_rows_max(int nx) {
     CoopShape sh;
     if (!pick_coop_shape(nx, sh)) return 0;
     // the most rows per workgroup of any shape instantiated for this x width
-    return sh.PX == 4 ? 64 : sh.PX == 8 ? 32 : 16;
+    return sh.PX == 4 ? 64 : sh.PX == 8 ? 32 : 24;
 }
 
 bool coop_supported(const mg_ops* ops, int precision, CoopKind kind) {
