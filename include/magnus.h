@@ -159,6 +159,10 @@ size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t preci
  * Errors: MG_EINVAL, MG_ESHAPE (P < 0, K < 1), MG_EUNSUPPORTED (precision or
  *         size without a kernel), MG_ENOMEM (ws too small), MG_EHIP.
  * P = 0 is a no-op.
+ * Coefficients piecewise constant in time (Remark piecewise) take one call
+ * per piece: the operators built from that piece's coefficients, the weights
+ * of that piece's fine increments (mg_iterated_integrals on a [P][Nf_piece]
+ * array with T = the piece's length) and the previous piece's uT as u0.
  * ------------------------------------------------------------------------ */
 mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
                           const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,

@@ -20,6 +20,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .expmv import expmv_series
+from .integrals import path_coefficients
 
 
 def magnus_log(basis: Sequence[sp.spmatrix], c: np.ndarray) -> sp.csr_matrix:
@@ -55,3 +56,25 @@ def iterated_magnus_paths(basis: Sequence[sp.spmatrix], coef: np.ndarray, u0: np
         start = u0 if u0.ndim == 1 else u0[p]
         out[p] = iterated_magnus(basis, coef[p], start, terms=terms)
     return out
+
+
+def piecewise_magnus_paths(pieces, dW: np.ndarray, u0: np.ndarray, order: int,
+                           terms: int = 20) -> np.ndarray:
+    """Coefficients that are deterministic and piecewise constant in time
+    (Remark piecewise): [0, T] is cut where the coefficients change and the
+    constant-coefficient scheme runs on each piece, its terminal value being
+    the initial value of the next piece.
+
+    pieces: (basis, T_piece, K_piece, Nf_piece) in time order, the basis of
+    that piece's coefficients and its length, Magnus steps and fine
+    increments; dW [P][sum of Nf_piece], the fine increments of the whole
+    interval; u0 [N] (shared) or [P][N]."""
+    u = np.asarray(u0, dtype=np.float64)
+    start = 0
+    for basis, Tp, Kp, Nfp in pieces:
+        coef = path_coefficients(dW[:, start:start + Nfp], Tp, Kp, order)
+        u = iterated_magnus_paths(basis, coef, u, terms=terms)
+        start += Nfp
+    if start != dW.shape[1]:
+        raise ValueError("the pieces do not cover the fine increments")
+    return u
