@@ -602,6 +602,17 @@ constexpr size_t resident_lds_bytes() {
            (size_t)2 * NW * sizeof(T) + 16;
 }
 
+// LDS of a resident workgroup that also holds the coefficient rows of the
+// current (path, step): the halo and reduction area, then NW*RJ rows of NBP.
+template <int PX, int NW, int RH, class T>
+constexpr size_t resident_ctab_offset() {
+    return (resident_lds_bytes<PX, NW, RH, T>() + 15) & ~(size_t)15;
+}
+template <int PX, int RJ, int NW, int RH, int NBP, class T>
+constexpr size_t resident_lds_with_ctab() {
+    return resident_ctab_offset<PX, NW, RH, T>() + (size_t)NW * RJ * NBP * sizeof(T);
+}
+
 // Table of one (path, step): 64-byte header, then rows of NBP coefficients.
 struct TableView {
     const char* base;
