@@ -343,9 +343,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
         const double es = tv.es();
         pflag |= tv.flag();
         // this step's coefficient rows, staged in LDS and read from there by
-        // every term (11 % faster than re-reading them through the scalar
-        // cache at 128^2; the FP64 kernel keeps the scalar reads, since the
-        // rows in VGPRs would make it spill)
+        // every term, one row ahead (13 % faster than re-reading them through
+        // the scalar cache at 128^2; the FP64 kernel keeps the scalar reads,
+        // since the rows in VGPRs make it spill)
         {
             constexpr int n16 = NW * RJ * NBP * (int)sizeof(T) / 16;
             static_assert(NW * RJ * NBP * sizeof(T) % 16 == 0, "row block not in 16-byte units");
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                 const int hp = tpar;
                 auto fb = [&] { halo.fetch_bot(hp, w, lane, bot); };
                 auto ft = [&] { halo.fetch_top(hp, w, lane, top); };
-                auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
+                const LdsRows<T, NBP> coef{rows};
                 const T invj = kFactors.inv_j[j];
                 T mc = 0, mf = 0;
                 // c_j = Y' c_{j-1} / j goes to `out`; F = hi + lo gains c_j (Kahan)

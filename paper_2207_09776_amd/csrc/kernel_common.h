@@ -322,6 +322,23 @@ __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
 
 // One application of the banded-Kronecker operator in "difference first" form,
 // from d into a separate output.  Because V_q acts along v and Dt along x,
+// Coefficient rows copied into LDS: apply_split requests them one row ahead
+// instead of two (an LDS read returns far sooner than a scalar-cache miss,
+// and every row held ahead costs NB registers per lane).
+template <class T, int NBP>
+struct LdsRows {
+    const T* rows;
+    __device__ T operator()(int r, int e) const { return rows[r * NBP + e]; }
+};
+template <class C>
+struct coef_ahead {
+    static constexpr int value = 2;
+};
+template <class T, int NBP>
+struct coef_ahead<LdsRows<T, NBP>> {
+    static constexpr int value = 1;
+};
+
 // V_q (x) Dt^q = (V_q (x) I)(I (x) Dt^q): each row's x differences e1 = Dt d and
 // e2 = Dt e1 (truncated to the grid) are formed once, and every output point is
 // a single FMA chain over the bands,
@@ -375,13 +392,18 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
         }
     };
     auto order = [](int i) { return i < RJ - RH ? i + RH : i - (RJ - RH); };
-    // coefficients of the current row and of the next two (requested two rows
-    // ahead: a miss in the scalar cache costs more than one row of work)
+    // coefficients of the current row and of the next AH (requested two rows
+    // ahead from the scalar cache, where a miss costs more than one row of
+    // work, one row ahead from LDS)
+    constexpr int AH = coef_ahead<Coef>::value;
+    static_assert(AH == 1 || AH == 2, "coefficients are requested one or two rows ahead");
     T cur[NB], nxt[NB], nx2[NB];
 #pragma unroll
     for (int e = 0; e < NB; ++e) cur[e] = coef(order(0), e);
+    if constexpr (AH == 2) {
 #pragma unroll
-    for (int e = 0; e < NB; ++e) nxt[e] = coef(order(1), e);
+        for (int e = 0; e < NB; ++e) nxt[e] = coef(order(1), e);
+    }
     // differences for the start of the first pass (rows RH - A .. RH + A - 1)
     if (QMAX >= 1) {
 #pragma unroll
@@ -394,10 +416,10 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
 #pragma unroll
     for (int i = 0; i < RJ; ++i) {
         const int r = order(i);
-        if (i + 2 < RJ) {
-            const int rn = order(i + 2);
+        if (i + AH < RJ) {
+            const int rn = order(i + AH);
 #pragma unroll
-            for (int e = 0; e < NB; ++e) nx2[e] = coef(rn, e);
+            for (int e = 0; e < NB; ++e) (AH == 2 ? nx2 : nxt)[e] = coef(rn, e);
         }
         if (r == FB) fetch_bot();
         if (r == FT) fetch_top();
@@ -444,7 +466,7 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
 #pragma unroll
         for (int e = 0; e < NB; ++e) {
             cur[e] = nxt[e];
-            nxt[e] = nx2[e];
+            if (AH == 2) nxt[e] = nx2[e];
         }
         __builtin_amdgcn_sched_barrier(0);
     }
