@@ -70,6 +70,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measure_upload(dW, ms_per_step, P, reps=5):
+    """The fine increments copied from pinned host memory to the device: the
+    boundary takes device pointers, so this PCIe copy sits outside the timed
+    step; reported beside it with the rate it would give if every step
+    brought its increments over."""
+    import torch
+    host = torch.empty(dW.shape, dtype=dW.dtype, pin_memory=True)
+    host.copy_(dW.cpu())
+    dst = torch.empty_like(dW)
+    dst.copy_(host, non_blocking=True)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(host, non_blocking=True)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    nbytes = dW.numel() * dW.element_size()
+    return {"bytes": nbytes, "ms": ms, "GBps": nbytes / ms / 1e6,
+            "paths_per_s_with_upload": P / ((ms_per_step + ms) / 1e3)}
+
+
 # ---------------------------------------------------------------- CPU oracle
 def _oracle_worker(args):
     """Runs in a child process: the oracle on a few paths, returns seconds."""
@@ -574,6 +597,10 @@ def main():
     streaming_bytes = float(terms) * N * 32
     extra = {"streaming_equivalent_GBps": streaming_bytes / k_avg_s / 1e9,
              "hbm_bytes_min_per_launch": float(P * N * 8 + N * 8 + mg.workspace_bytes(ops, P, K))}
+    upload = measure_upload(dW, ms_per_step, P)
+    log(f"dW upload from pinned host memory: {upload['bytes'] / 2**20:.0f} MiB in "
+        f"{upload['ms']:.3f} ms ({upload['GBps']:.1f} GB/s); with it "
+        f"{upload['paths_per_s_with_upload']:.0f} paths/s")
 
     # compensated FP32 at the same K: errors must agree within 1 % of the FP64 error
     fp32c = None
@@ -718,6 +745,7 @@ def main():
         "flagged_paths": nflag,
         "roofline": roofline,
         "hbm": extra,
+        "upload": upload,
         "euler": euler,
         "fp32c": fp32c,
         "cpu_baseline": cpu,
