@@ -269,6 +269,10 @@ COOP_CASES = [
     ("coop-200x150-m2-f64", 200, 150, -5.0, 5.0, 2, 2, 2, 256, 0.25, "fp64", 1e-10),
     ("coop-256x256-m2-f32c", 256, 256, -5.0, 5.0, 2, 3, 2, 256, 0.25, "fp32c", 1e-5),
     ("coop-512x512-m2-f32c", 512, 512, -5.0, 5.0, 2, 1, 1, 64, 0.05, "fp32c", 1e-5),
+    # nx > 512: workgroups of 24 rows; 520 leaves most of the last lane's 16
+    # points empty, and 40 and 60 rows leave the last slab part empty
+    ("coop-520x40-m2-f32c", 520, 40, -5.0, 5.0, 2, 2, 2, 256, 0.05, "fp32c", 1e-5),
+    ("coop-1024x60-m3-f32c", 1024, 60, -5.0, 5.0, 3, 2, 2, 256, 0.02, "fp32c", 1e-5),
     # 8 paths: the plan places 8 groups, each on one XCD, and the members
     # exchange through that XCD's L2 (the other cases use agent scope)
     ("coop-256x256-m2-f64-p8", 256, 256, -5.0, 5.0, 2, 8, 2, 256, 0.05, "fp64", 1e-10),
