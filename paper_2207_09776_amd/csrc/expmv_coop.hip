@@ -646,6 +646,12 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, F32C, 0); \
     return hipErrorInvalidValue;
 #define MG_COOP_SHAPES_ND(PX, RJ, NW, FULLX, F32C, CALL)                                       \
+    if (ops->ND == 3) {                                                                        \
+        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, F32C, 3); \
+        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, F32C, 3); \
+        return hipErrorInvalidValue;                                                           \
+    }                                                                                          \
+    if (ops->ND != MG_MAX_XDIAG) return hipErrorInvalidValue;                                  \
     if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, F32C, MG_MAX_XDIAG); \
     return hipErrorInvalidValue;

@@ -630,11 +630,17 @@ hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE,
 // constant-coefficient Langevin operator, (2,1,1,2) its order 3, (3,3,3,2)
 // v-dependent coefficients.  B and A (Euler) only carry Dt^0 and Dt^1.
 #define MG_FOR_SHAPE(PX, RJ, NW, FULLX, CALL)                                                  \
-    if (ops->ND > 0) {                                                                         \
+    if (ops->ND == 3) {                                                                        \
+        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 3); \
+        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 3); \
+        return hipErrorInvalidValue;                                                           \
+    }                                                                                          \
+    if (ops->ND == MG_MAX_XDIAG) {                                                             \
         if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, MG_MAX_XDIAG); \
         if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG); \
         return hipErrorInvalidValue;                                                           \
     }                                                                                          \
+    if (ops->ND > 0) return hipErrorInvalidValue;                                              \
     if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 0); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 0); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, 0); \

@@ -21,12 +21,12 @@
 //
 // Coefficients that depend on x add terms W_{l,t} (x) diag(a_t) (t < ND, the
 // x vectors a_t shared by all l); their bands (radius RW) follow the three V
-// bands in each row, so NB = sum_q (2R[q]+1) + ND (2RW+1).  ND is 0 or
-// MG_MAX_XDIAG (unused factors are zero).
+// bands in each row, so NB = sum_q (2R[q]+1) + ND (2RW+1).  ND is 0, 3 (for
+// one to three factors) or MG_MAX_XDIAG (unused factors are zero).
 // ---------------------------------------------------------------------------
 constexpr int MG_NBASIS = 6;
 constexpr int MG_HDR = 8;          // table header entries (doubles)
-constexpr int MG_MAX_XDIAG = 4;    // x-dependent factors the kernels take
+constexpr int MG_MAX_XDIAG = 4;    // most x-dependent factors the kernels take
 constexpr int MG_XDIAG_RADIUS = 2; // band radius of their v factors
 
 struct mg_ops {

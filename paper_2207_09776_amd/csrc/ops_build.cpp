@@ -398,8 +398,9 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     ops->order = order;
     ops->nactive = nact;
     for (int q = 0; q < 3; ++q) ops->R[q] = R[q];
-    // x-dependent factors: the kernels take a fixed count (unused ones are zero)
-    ops->ND = nd > 0 ? MG_MAX_XDIAG : 0;
+    // x-dependent factors: the kernels are built for 3 and for 4 factors
+    // (unused ones are zero; the variable-coefficient workloads use 3)
+    ops->ND = nd > 0 ? (nd <= 3 ? 3 : MG_MAX_XDIAG) : 0;
     ops->RW = nd > 0 ? MG_XDIAG_RADIUS : 0;
     ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (2 * R[2] + 1) + ops->ND * (2 * ops->RW + 1);
     ops->NBP = (ops->NB + 1) & ~1;

@@ -102,6 +102,46 @@ def test_variable_euler_matches_oracle(nx, nv, NE, T):
     assert int(flags.abs().sum()) == 0
 
 
+def four_factor_coefficients():
+    """The variable workload plus a zeroth-order term h(x, v) whose x profile
+    lies outside the span of the diffusion's three: four x-dependent
+    factors."""
+    base = wl.langevin_variable_sigma_beta()
+    return wl.Coefficients(fx=base.fx, gvv=base.gvv, sv=base.sv,
+                           h=lambda x, v: 0.05 * np.cos(np.pi * x / 5.0) * np.exp(-v * v / 4.0))
+
+
+@pytest.mark.parametrize("nx,nv,P,prec,tol", [(64, 64, 2, "fp64", 1e-10), (64, 64, 2, "fp32c", 1e-5),
+                                              (200, 150, 2, "fp64", 1e-10)])
+def test_four_x_factors_match_oracle(nx, nv, P, prec, tol):
+    """The kernels are built for three and for four x-dependent factors; the
+    variable workload takes the three-factor build, this set the four-factor
+    one (its table rows carry four factor bands, which the workspace size
+    shows on the register-resident grid)."""
+    say(f"four x-factors {nx}x{nv} {prec}")
+    g, B, A, basis, ops = setup_problem(nx, nv, -5.0, 5.0, four_factor_coefficients(), 2)
+    if nx <= 128:
+        # a table row: the bands of V0, V1, V2 (5 + 3 + 1 entries) and one
+        # radius-2 band per factor, padded to an even count
+        def row(nd):
+            return (9 + nd * 5 + 1) // 2 * 2
+        elem = 8 if prec == "fp64" else 4
+        assert mg.workspace_bytes(ops, 1, 1, prec) == 64 + nv * row(4) * elem
+        _, _, _, _, ops3 = setup_problem(nx, nv, -5.0, 5.0, wl.langevin_variable_sigma_beta(), 2)
+        assert mg.workspace_bytes(ops3, 1, 1, prec) == 64 + nv * row(3) * elem
+    K, Nf, T = 4, 256, (1.0 if nx <= 128 else 0.1)
+    dW = wl.brownian_increments(37, P, Nf, T=T)
+    u0 = wl.gaussian_density(nx, nv, -5, 5, -5, 5, 0.25).reshape(-1)
+    coef, _ = mg.iterated_integrals(to_dev(dW), T, K, 2)
+    uT, flags, _ = mg.magnus_expmv(ops, coef, to_dev(u0), precision=prec)
+    torch.cuda.synchronize()
+    assert int(flags.abs().sum()) == 0, flags.cpu().numpy()
+    want = magnus.iterated_magnus_paths(basis, integrals.path_coefficients(dW, T, K, 2), u0)
+    for p in range(P):
+        e = rel(uT[p].cpu().numpy(), want[p])
+        assert e <= tol, (nx, nv, prec, p, e)
+
+
 def test_variable_above_512_is_reported_unsupported():
     """x-dependent factors are taken up to nx = 512: a wider grid fails with
     MG_EUNSUPPORTED (Magnus and Euler) instead of running."""
