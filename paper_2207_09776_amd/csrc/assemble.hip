@@ -39,6 +39,7 @@ struct AsmArgs {
     int f32;                   // rows in FP32 (compensated form) instead of FP64
     int nx, nv, nv_pad, K, NBP, nact;
     int R0, R1, R2;
+    int qmax;                  // V2 (Dt^2) entries are in the row only for qmax >= 2
     int ND, RW;                // x-dependent factors (0: none) and their band radius
     const double* xstat;       // per factor {sum, midpoint, half-width, 0}
     int use24;                 // theta table for 2^-24 instead of 2^-53
@@ -76,7 +77,8 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
     const int64_t pk = blockIdx.x;
     const double* c = a.coef + pk * 6;
     const int t = threadIdx.x;
-    const int o0 = 0, o1 = 2 * a.R0 + 1, o2 = o1 + 2 * a.R1 + 1, o3 = o2 + 2 * a.R2 + 1;
+    const bool v2 = a.qmax >= 2;
+    const int o0 = 0, o1 = 2 * a.R0 + 1, o2 = o1 + 2 * a.R1 + 1, o3 = o2 + (v2 ? 2 * a.R2 + 1 : 0);
     const int wl = 2 * a.RW + 1;
     const int nx = a.nx, nv = a.nv;
 
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
     const double trDt2 = nx >= 2 ? -(2.0 * nx - 2.0) : 0.0;
     double tr = 0.0;
     for (int j = t; j < nv; j += kThreads) {
-        tr += nx * coeff(a, c, j, o0 + a.R0) + trDt2 * coeff(a, c, j, o2 + a.R2);
+        tr += nx * coeff(a, c, j, o0 + a.R0) + (v2 ? trDt2 * coeff(a, c, j, o2 + a.R2) : 0.0);
         for (int f = 0; f < a.ND; ++f) tr += coeff(a, c, j, o3 + f * wl + a.RW) * a.xstat[4 * f];
     }
     tr = block_reduce(tr, red, false);
@@ -103,7 +105,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
             const int b = jp - j;
             const double a0 = (b >= -a.R0 && b <= a.R0) ? coeff(a, c, j, o0 + b + a.R0) : 0.0;
             const double a1 = (b >= -a.R1 && b <= a.R1) ? coeff(a, c, j, o1 + b + a.R1) : 0.0;
-            const double a2 = (b >= -a.R2 && b <= a.R2) ? coeff(a, c, j, o2 + b + a.R2) : 0.0;
+            const double a2 = (v2 && b >= -a.R2 && b <= a.R2) ? coeff(a, c, j, o2 + b + a.R2) : 0.0;
             double d0 = a0 - (b == 0 ? mu : 0.0), spread = 0.0;
             if (b >= -a.RW && b <= a.RW)
                 for (int f = 0; f < a.ND; ++f) {
@@ -191,6 +193,7 @@ hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int
     a.R0 = ops->R[0];
     a.R1 = ops->R[1];
     a.R2 = ops->R[2];
+    a.qmax = ops->qmax;
     a.ND = ops->ND;
     a.RW = ops->RW;
     a.xstat = ops->ND > 0 ? ops->xdiag_dev + (size_t)ops->ND * ops->grid.nx : nullptr;

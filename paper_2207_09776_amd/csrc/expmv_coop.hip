@@ -348,7 +348,7 @@ template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, 
 __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
     constexpr int RW = NW * RJ;
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
@@ -527,7 +527,7 @@ template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, 
 __global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
     using T = double;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
     constexpr int RW = NW * RJ;
     extern __shared__ double lds_d[];
     T* lds = lds_d;

@@ -116,9 +116,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, double tol,
     int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag) {
     using T = double;
-    using BD = Bands<R0, R1, R2>;
+    using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
@@ -275,9 +275,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, float tol,
     int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag) {
     using T = float;
-    using BD = Bands<R0, R1, R2>;
+    using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
@@ -461,9 +461,9 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     const double* __restrict__ dWE, int NE, double dt, int32_t* __restrict__ flags,
     const double* __restrict__ xdiag) {
     using T = double;
-    using BD = Bands<R0, R1, R2>;
+    using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    constexpr int NBP = table_stride<R0, R1, R2, ND>();
+    constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
     extern __shared__ double lds[];
     Halo<PX, RJ, NW, RH, T> halo{lds};
     int* sflag = reinterpret_cast<int*>(lds + halo_bytes<PX, NW, RH, T>() / sizeof(T));
@@ -588,7 +588,7 @@ hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64
                      int32_t* stats, int32_t* flags, hipStream_t s) {
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     // the tables must have the row layout the kernel reads
-    if (ops->NBP != table_stride<R0, R1, R2, ND>()) return hipErrorInvalidValue;
+    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>()) return hipErrorInvalidValue;
     if (precision == MG_FP64) {
         constexpr size_t lds = resident_lds_bytes<PX, NW, RH, double>();
         auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
@@ -599,7 +599,7 @@ hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64
                            ops->xdiag_dev);
     } else {
         constexpr size_t lds =
-            resident_lds_with_ctab<PX, RJ, NW, RH, table_stride<R0, R1, R2, ND>(), float>();
+            resident_lds_with_ctab<PX, RJ, NW, RH, table_stride<R0, R1, R2, QMAX, ND>(), float>();
         auto kern = expmv_resident_f32c_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
@@ -614,7 +614,7 @@ template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, 
 hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE, int NE,
                      double dt, int32_t* flags, hipStream_t s) {
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    if (ops->NBP != table_stride<R0, R1, R2, ND>()) return hipErrorInvalidValue;
+    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>()) return hipErrorInvalidValue;
     constexpr size_t lds = halo_bytes<PX, NW, RH, double>() + 16;
     auto kern = euler_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

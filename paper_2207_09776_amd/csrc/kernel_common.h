@@ -115,12 +115,13 @@ __device__ inline T wave_max_dpp(T x) {
     return lane_value<63>(x);
 }
 
-template <int R0, int R1, int R2>
+template <int R0, int R1, int R2, int Q = 2>
 struct Bands {
     static constexpr int RH = (R0 > R1 ? (R0 > R2 ? R0 : R2) : (R1 > R2 ? R1 : R2));
     static constexpr int O1 = 2 * R0 + 1;
     static constexpr int O2 = O1 + 2 * R1 + 1;
-    static constexpr int NB = O2 + 2 * R2 + 1;
+    // the V2 band is stored only where Dt^2 occurs (Q = highest power of Dt)
+    static constexpr int NB = O2 + (Q >= 2 ? 2 * R2 + 1 : 0);
     static constexpr int NBP = (NB + 1) & ~1;
 };
 
@@ -132,7 +133,7 @@ struct Bands {
 template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, class T, class In,
           class Coef>
 __device__ inline void apply_operator(In din, Coef coef, int lane, int nx, T (&out)[RJ][PX]) {
-    using BD = Bands<R0, R1, R2>;
+    using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int NB = BD::NB;
     T cur[NB], nxt[NB];
 #pragma unroll
@@ -201,7 +202,7 @@ template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, 
 __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
                                      const T (&bot)[RH][PX], Coef coef, int lane, int nx,
                                      Emit emit) {
-    using BD = Bands<R0, R1, R2>;
+    using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int NB = BD::NB;
     auto din = [&](int rr, int q) -> T {
         if (rr < 0) return top[rr + RH][q];
@@ -289,7 +290,7 @@ template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, 
 __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
                                        const T (&bot)[RH][PX], Coef coef, XA xa, int lane, int nx,
                                        Emit emit) {
-    constexpr int NBM = Bands<R0, R1, R2>::NB;
+    constexpr int NBM = Bands<R0, R1, R2, QMAX>::NB;
     constexpr int WL = 2 * RW + 1;
     static_assert(RW <= RH, "halo narrower than the x-dependent factors");
     apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(
@@ -355,7 +356,7 @@ template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, 
 __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&top)[RH][PX],
                                    T (&bot)[RH][PX], FetchBot fetch_bot, FetchTop fetch_top,
                                    Coef coef, int lane, int nx, Emit emit) {
-    using BD = Bands<R0, R1, R2>;
+    using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int NB = BD::NB;
     constexpr int A2 = QMAX >= 2 ? R2 : 0;                    // e2 rows needed ahead
     constexpr int A1 = QMAX >= 1 ? (A2 > R1 ? A2 : R1) : 0;   // e1 rows needed ahead
@@ -483,7 +484,7 @@ __device__ inline void apply_split_x(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (
                                      T (&bot)[RH][PX], FetchBot fetch_bot, FetchTop fetch_top,
                                      Coef coef, const T (&xa)[ND][PX], int lane, int nx,
                                      Emit emit) {
-    constexpr int NBM = Bands<R0, R1, R2>::NB;
+    constexpr int NBM = Bands<R0, R1, R2, QMAX>::NB;
     constexpr int WL = 2 * RW + 1;
     static_assert(RW <= RH, "halo narrower than the x-dependent factors");
     auto din = [&](int rr, int q) -> T {
@@ -537,9 +538,9 @@ constexpr int halo_rows() {
 
 // Coefficients per table row (padded to an even count): the V bands, then the
 // bands of the x-dependent factors.
-template <int R0, int R1, int R2, int ND>
+template <int R0, int R1, int R2, int QMAX, int ND>
 constexpr int table_stride() {
-    return (Bands<R0, R1, R2>::NB + ND * (2 * MG_XDIAG_RADIUS + 1) + 1) & ~1;
+    return (Bands<R0, R1, R2, QMAX>::NB + ND * (2 * MG_XDIAG_RADIUS + 1) + 1) & ~1;
 }
 
 // apply_split, or apply_split_x when the operator has x-dependent factors.

@@ -17,11 +17,12 @@
 // is the raw x difference (D^x = Dt / (2 dx)); the factor (1/(2dx))^q is folded
 // into V_{l,q}.  V_{l,q} is an nv x nv band matrix with radius R[q]; row j is
 // stored as 2R[q]+1 entries for columns j-R[q] .. j+R[q].  The bands of the
-// three q are concatenated per row: NB = sum_q (2R[q]+1) doubles, padded to NBP.
+// q <= qmax are concatenated per row: NB = sum_{q <= qmax} (2R[q]+1) doubles,
+// padded to NBP (a row holds no V2 band where Dt^2 does not occur).
 //
 // Coefficients that depend on x add terms W_{l,t} (x) diag(a_t) (t < ND, the
 // x vectors a_t shared by all l); their bands (radius RW) follow the three V
-// bands in each row, so NB = sum_q (2R[q]+1) + ND (2RW+1).  ND is 0, 3 (for
+// bands in each row, so NB = sum_{q <= qmax} (2R[q]+1) + ND (2RW+1).  ND is 0, 3 (for
 // one to three factors) or MG_MAX_XDIAG (unused factors are zero).
 // ---------------------------------------------------------------------------
 constexpr int MG_NBASIS = 6;

@@ -402,7 +402,10 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     // (unused ones are zero; the variable-coefficient workloads use 3)
     ops->ND = nd > 0 ? (nd <= 3 ? 3 : MG_MAX_XDIAG) : 0;
     ops->RW = nd > 0 ? MG_XDIAG_RADIUS : 0;
-    ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (2 * R[2] + 1) + ops->ND * (2 * ops->RW + 1);
+    // V2 (the Dt^2 factor) has entries in the row only where Dt^2 occurs
+    const int nq = ops->qmax >= 2 ? 3 : 2;
+    ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (nq == 3 ? 2 * R[2] + 1 : 0) +
+              ops->ND * (2 * ops->RW + 1);
     ops->NBP = (ops->NB + 1) & ~1;
     ops->xdiag_host.assign((size_t)ops->ND * nx, 0.0);
     ops->xstat_host.assign((size_t)ops->ND * 4, 0.0);
@@ -434,7 +437,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         for (int j = 0; j < nv; ++j) {
             double* row = ops->basis_host.data() + ((size_t)l * ops->nv_pad + j) * ops->NBP;
             int off = 0;
-            for (int q = 0; q < 3; ++q) {
+            for (int q = 0; q < nq; ++q) {
                 for (int o = -R[q]; o <= R[q]; ++o) row[off + o + R[q]] = M[l].V[q].get(j, j + o) * fold[q];
                 off += 2 * R[q] + 1;
             }

@@ -121,10 +121,10 @@ def test_four_x_factors_match_oracle(nx, nv, P, prec, tol):
     say(f"four x-factors {nx}x{nv} {prec}")
     g, B, A, basis, ops = setup_problem(nx, nv, -5.0, 5.0, four_factor_coefficients(), 2)
     if nx <= 128:
-        # a table row: the bands of V0, V1, V2 (5 + 3 + 1 entries) and one
-        # radius-2 band per factor, padded to an even count
+        # a table row: the bands of V0 and V1 (5 + 3 entries; no Dt^2 term at
+        # order 2) and one radius-2 band per factor, padded to an even count
         def row(nd):
-            return (9 + nd * 5 + 1) // 2 * 2
+            return (8 + nd * 5 + 1) // 2 * 2
         elem = 8 if prec == "fp64" else 4
         assert mg.workspace_bytes(ops, 1, 1, prec) == 64 + nv * row(4) * elem
         _, _, _, _, ops3 = setup_problem(nx, nv, -5.0, 5.0, wl.langevin_variable_sigma_beta(), 2)
