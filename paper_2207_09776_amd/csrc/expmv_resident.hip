@@ -18,7 +18,8 @@
 //                                             through DPP wave shifts)
 // The band coefficients of a row are the same for every lane of the wave: the
 // FP64 kernel reads them with scalar loads, the FP32 kernel from a copy of
-// the step's rows in LDS.  One barrier per Taylor term orders the halo
+// the step's rows in LDS (scalar loads at one point per lane).  One barrier
+// per Taylor term orders the halo
 // exchange; the same barrier publishes the per-wave inf-norms used by the
 // early-termination test of the Taylor sum.
 //
@@ -268,6 +269,13 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     if (flags && threadIdx.x == 0) flags[p] = *sflag | pflag;
 }
 
+// The FP32C kernel copies a step's coefficient rows into LDS when a lane
+// holds two or more points per row.
+template <int PX>
+constexpr bool f32c_stages_rows() {
+    return PX >= 2;
+}
+
 // Compensated FP32 form (see the file header).
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
@@ -284,6 +292,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
     T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);
     T* red2 = red + 2 * NW * 2;
     int* sflag = reinterpret_cast<int*>(red2 + 2 * NW);
+    // coefficient rows staged in LDS from two points per lane on
+    constexpr bool kStageRows = f32c_stages_rows<PX>();
     T* ctab = reinterpret_cast<T*>(reinterpret_cast<char*>(lds_d) +
                                    resident_ctab_offset<PX, NW, RH, T>());
 
@@ -344,9 +354,10 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
         pflag |= tv.flag();
         // this step's coefficient rows, staged in LDS and read from there by
         // every term, one row ahead (13 % faster than re-reading them through
-        // the scalar cache at 128^2; the FP64 kernel keeps the scalar reads,
+        // the scalar cache at 128^2; at one point per lane the copy costs
+        // more than it saves, and the FP64 kernel keeps the scalar reads,
         // since the rows in VGPRs make it spill)
-        {
+        if constexpr (kStageRows) {
             constexpr int n16 = NW * RJ * NBP * (int)sizeof(T) / 16;
             static_assert(NW * RJ * NBP * sizeof(T) % 16 == 0, "row block not in 16-byte units");
             const uint4* src = reinterpret_cast<const uint4*>(tv.rows<T>());
@@ -355,7 +366,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
             for (int i = threadIdx.x; i < n16; i += 64 * NW) dst[i] = src[i];
             __syncthreads();
         }
-        const T* rows = ctab + (size_t)row0 * NBP;
+        const T* rows = (kStageRows ? ctab : tv.rows<T>()) + (size_t)row0 * NBP;
         int terms = 0;
         for (int sub = 0; sub < s; ++sub) {
             T A[RJ][PX], B[RJ][PX];
@@ -380,7 +391,12 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                 const int hp = tpar;
                 auto fb = [&] { halo.fetch_bot(hp, w, lane, bot); };
                 auto ft = [&] { halo.fetch_top(hp, w, lane, top); };
-                const LdsRows<T, NBP> coef{rows};
+                const auto coef = [&] {
+                    if constexpr (kStageRows)
+                        return LdsRows<T, NBP>{rows};
+                    else
+                        return [rows](int r, int e) -> T { return rows[r * NBP + e]; };
+                }();
                 const T invj = kFactors.inv_j[j];
                 T mc = 0, mf = 0;
                 // c_j = Y' c_{j-1} / j goes to `out`; F = hi + lo gains c_j (Kahan)
@@ -599,7 +615,10 @@ hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64
                            ops->xdiag_dev);
     } else {
         constexpr size_t lds =
-            resident_lds_with_ctab<PX, RJ, NW, RH, table_stride<R0, R1, R2, QMAX, ND>(), float>();
+            f32c_stages_rows<PX>()
+                ? resident_lds_with_ctab<PX, RJ, NW, RH, table_stride<R0, R1, R2, QMAX, ND>(),
+                                         float>()
+                : resident_lds_bytes<PX, NW, RH, float>();
         auto kern = expmv_resident_f32c_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
