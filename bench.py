@@ -48,7 +48,7 @@ EULER_FLOPS_PT = 2 * 5 + 1            # u + (dt B + dW A) u: 5 non-zeros per row
 TRAFFIC = {
     # (source hash, workload): (bytes read, bytes written) per launch;
     # profiles/expmv_resident_counters_const-128-p1024-m2-k16.txt
-    ("fbbe4ba3a5569ba5", "const-128-p1024-m2-k16"): (133708 * 1024 * 2.000, 131110 * 1024 * 1.000),
+    ("68df813b853601cf", "const-128-p1024-m2-k16"): (133691 * 1024 * 2.000, 131110 * 1024 * 1.000),
 }
 
 
