@@ -70,6 +70,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measure_copy_peak(reps=5):
+    """Bytes read plus written per second by a plain 1 GiB device-to-device
+    copy: the HBM rate a simple streaming kernel reaches on this GPU."""
+    import torch
+    src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del src, dst
+    return 2 * 2 ** 30 / ms / 1e6
+
+
 def measure_upload(dW, ms_per_step, P, reps=5):
     """The fine increments copied from pinned host memory to the device: the
     boundary takes device pointers, so this PCIe copy sits outside the timed
@@ -597,6 +616,12 @@ def main():
     streaming_bytes = float(terms) * N * 32
     extra = {"streaming_equivalent_GBps": streaming_bytes / k_avg_s / 1e9,
              "hbm_bytes_min_per_launch": float(P * N * 8 + N * 8 + mg.workspace_bytes(ops, P, K))}
+    copy_gbps = measure_copy_peak()
+    extra["copy_kernel_GBps"] = copy_gbps
+    extra["copy_kernel_frac_of_8TBps"] = copy_gbps / 8000.0
+    if roofline["traffic"] is not None:
+        extra["measured_GBps"] = roofline["traffic"] / k_avg_s / 1e9
+    log(f"plain 1 GiB device copy: {copy_gbps:.0f} GB/s read + write ({copy_gbps / 8000:.2f} of 8 TB/s)")
     upload = measure_upload(dW, ms_per_step, P)
     log(f"dW upload from pinned host memory: {upload['bytes'] / 2**20:.0f} MiB in "
         f"{upload['ms']:.3f} ms ({upload['GBps']:.1f} GB/s); with it "
