@@ -153,7 +153,8 @@ size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t preci
  *   uT        : device FP64, [P][N] output (may not alias coef or ws).
  *   precision : MG_FP64 or MG_FP32C.
  *   tol       : Taylor tolerance; <= 0 selects 2^-53 (FP64) / 2^-24 (FP32C).
- *   ws        : device workspace of ws_bytes >= mg_workspace_bytes(...).
+ *   ws        : device workspace of ws_bytes >= mg_workspace_bytes(...),
+ *               16-byte aligned (MG_EINVAL otherwise).
  *   stats     : device int32 [P][K][2] = (Taylor terms applied, s), or NULL.
  *   flags     : device int32 [P] (MG_FLAG_* bits), or NULL.
  * Errors: MG_EINVAL, MG_ESHAPE (P < 0, K < 1), MG_EUNSUPPORTED (precision or
@@ -203,7 +204,7 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
  * whole call (mg_last_error names the job) and no kernel runs.  The jobs then
  * run in order on `stream`.
  *   jobs : host array of njobs descriptors;  ws : device workspace of
- *          ws_bytes >= mg_workspace_bytes_multi(jobs, njobs).
+ *          ws_bytes >= mg_workspace_bytes_multi(jobs, njobs), 16-byte aligned.
  * Errors: those of mg_magnus_expmv; MG_EINVAL (njobs < 0, NULL jobs).
  * njobs = 0 is a no-op.
  * ------------------------------------------------------------------------ */
@@ -279,7 +280,8 @@ mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const d
  *   precision must be MG_FP64.
  *   ws    : device workspace of ws_bytes >= mg_euler_workspace_bytes(ops, P)
  *           (the exchange area of grids with nx > 128, where several
- *           workgroups share a path); may be NULL when that size is 0.
+ *           workgroups share a path), 16-byte aligned; may be NULL when that
+ *           size is 0.
  * Errors: MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED (nx > 512), MG_ENOMEM (ws
  * too small), MG_EHIP.  P = 0 or NE = 0 is a no-op.
  * ------------------------------------------------------------------------ */

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <limits>
@@ -253,6 +254,13 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
+namespace {
+// Workspaces hold FP64 tables read in 16-byte units and the 32/64-bit words
+// of the cooperative exchange: they must start on a 16-byte boundary (device
+// allocations start on much larger ones).
+bool ws_aligned(const void* ws) { return ((uintptr_t)ws & 15) == 0; }
+}  // namespace
+
 mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
                           const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
                           double tol, void* ws, size_t ws_bytes, int32_t* stats, int32_t* flags,
@@ -263,6 +271,7 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
     mg_status st = expmv_prepare(c, where);
     if (st != MG_OK || P == 0) return st;
     if (!ws) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (!ws_aligned(ws)) return mg_fail(MG_EINVAL, where + ": workspace not 16-byte aligned");
     if (ws_bytes < c.need)
         return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
     return expmv_launch(c, (char*)ws, (hipStream_t)stream, where);
@@ -292,6 +301,7 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
     if (P == 0) return mg_fail(MG_ESHAPE, where + ": need P >= 1");
     if (reps < 1 || reps > 100) return mg_fail(MG_EINVAL, where + ": reps must be in 1..100");
     if (!ws) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (!ws_aligned(ws)) return mg_fail(MG_EINVAL, where + ": workspace not 16-byte aligned");
     if (ws_bytes < c.need)
         return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
     std::string rep;
@@ -513,6 +523,8 @@ mg_status mg_magnus_expmv_multi(const mg_job* jobs, int32_t njobs, void* ws, siz
         calls.push_back(c);
     }
     if (total > 0 && !ws) return mg_fail(MG_EINVAL, "mg_magnus_expmv_multi: NULL workspace");
+    if (total > 0 && !ws_aligned(ws))
+        return mg_fail(MG_EINVAL, "mg_magnus_expmv_multi: workspace not 16-byte aligned");
     if (ws_bytes < total)
         return mg_fail(MG_ENOMEM,
                        "mg_magnus_expmv_multi: workspace smaller than mg_workspace_bytes_multi()");
@@ -571,6 +583,7 @@ mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* d
         if (!ws || ws_bytes < plan.bytes)
             return mg_fail(MG_ENOMEM, "mg_euler_step: workspace too small (need " +
                                           std::to_string(plan.bytes) + " bytes)");
+        if (!ws_aligned(ws)) return mg_fail(MG_EINVAL, "mg_euler_step: workspace not 16-byte aligned");
     }
     TimingScope ts("euler", s);
     hipError_t e = fam == Family::Resident

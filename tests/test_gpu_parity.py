@@ -169,6 +169,41 @@ def test_zero_paths_is_noop_and_nonfinite_path_is_flagged():
     assert rel(uT[2].cpu().numpy(), good[1]) <= 1e-10
 
 
+def test_unaligned_workspace_is_rejected():
+    """A workspace must start on a 16-byte boundary (tables are read in
+    16-byte units, the cooperative exchange uses 32- and 64-bit atomics): one
+    that does not fails with MG_EINVAL before anything runs, for the resident
+    and the cooperative Taylor kernels and for the cooperative Euler kernel;
+    the output is left untouched."""
+    say("unaligned workspace")
+    coeffs = wl.langevin_constant(1.0, 0.5)
+    for n in (32, 160):
+        g, B, A, basis, ops = setup_problem(n, n, -4.0, 4.0, coeffs, 2)
+        dW = wl.brownian_increments(5, 2, 64)
+        coef, _ = mg.iterated_integrals(to_dev(dW), 1.0, 4, 2)
+        u0 = torch.ones(n * n, dtype=torch.float64, device=DEV)
+        need = mg.workspace_bytes(ops, 2, 4)
+        ws = torch.empty(need + 64, dtype=torch.uint8, device=DEV)
+        uT = torch.full((2, n * n), 7.0, dtype=torch.float64, device=DEV)
+        with pytest.raises(mg.MagnusError) as ei:
+            mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws[8:])
+        assert ei.value.code == mg.MG_EINVAL, (n, ei.value)
+        torch.cuda.synchronize()
+        assert bool((uT == 7.0).all())
+        # the aligned slice of the same buffer runs
+        mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws[16:])
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(uT).all())
+        if n > 128:
+            ew = mg.euler_workspace_bytes(ops, 2)
+            wse = torch.empty(ew + 64, dtype=torch.uint8, device=DEV)
+            u = torch.ones((2, n * n), dtype=torch.float64, device=DEV)
+            dWE = torch.zeros((2, 4), dtype=torch.float64, device=DEV)
+            with pytest.raises(mg.MagnusError) as ei:
+                mg.euler_step(ops, u, dWE, 1e-5, ws=wse[8:])
+            assert ei.value.code == mg.MG_EINVAL
+
+
 def test_repeat_runs_are_bitwise_identical():
     say("magnus determinism")
     n = 64
