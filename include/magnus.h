@@ -136,6 +136,26 @@ mg_status mg_free_operators(mg_ops* ops);
 mg_status mg_iterated_integrals(const double* dW, int64_t P, int64_t Nf, double T, int32_t K,
                                 int32_t order, double* coef, double* pathstat, void* stream);
 
+/* --------------------------------------------------------------------------
+ * mg_iterated_integrals_steps  (eq. (MagnusFormulas) with a step size per
+ *                               path; Remark "stepSizeControl")
+ *
+ * As mg_iterated_integrals, with path p split into K[p] sub-intervals of
+ * length T/K[p]: coef[p][k] for k < K[p] are that path's weights and
+ * coef[p][k] for K[p] <= k < Kmax are zero (a zero step is the identity in
+ * mg_magnus_expmv, which then takes K = Kmax for the whole batch).
+ *   K       : device int32 [P], each a divisor of Nf in 1 .. Kmax; a path
+ *             whose count is not gets NaN weights (and NaN pathstat), which
+ *             mg_magnus_expmv flags as non-finite.
+ *   coef    : device FP64 [P][Kmax][6] output;  pathstat as in
+ *             mg_iterated_integrals (may be NULL).
+ * Errors: MG_EINVAL (NULL, T <= 0, order outside 1..3), MG_ESHAPE (P < 0,
+ * Kmax < 1, Nf < 1).  P = 0 is a no-op.
+ * ------------------------------------------------------------------------ */
+mg_status mg_iterated_integrals_steps(const double* dW, int64_t P, int64_t Nf, double T,
+                                      const int32_t* K, int32_t Kmax, int32_t order, double* coef,
+                                      double* pathstat, void* stream);
+
 /* Bytes of device workspace mg_magnus_expmv needs for P paths and K steps. */
 size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t precision);
 
@@ -266,6 +286,32 @@ mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const d
                                  int32_t factor, int32_t Kmax, double tol, int32_t precision,
                                  int32_t* K_out, double* gap_out, int32_t* accepted,
                                  void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_select_magnus_steps_per_path  (Remark "stepSizeControl", per trajectory)
+ *
+ * The same ladder as mg_select_magnus_steps, decided per path: every path
+ * runs rung K = K0, K0*factor, ... (each dividing Nf and <= Kmax) until its
+ * own distance ||u3_p - u2_p||_F / ||u3_p||_F is <= tol; K_out[p] is that K
+ * (or the last K tried), gap_out[p] its distance (+inf for a flagged or
+ * non-finite path).  The ladder stops once every path is accepted.  The
+ * counts feed mg_iterated_integrals_steps, so that one batch runs each path
+ * with its own step size.
+ *   ops2, ops3 : operators of orders 2 and 3 on the same grid and
+ *                coefficients.
+ *   dW         : device FP64 [P][Nf];  u0 : device FP64 [N].
+ *   K_out      : host int32 [P];  gap_out : host FP64 [P];
+ *   n_accepted : host, the number of paths within tol.
+ * A set-up call: it allocates its own device buffers and waits for the
+ * stream.
+ * Errors: as mg_select_magnus_steps.
+ * ------------------------------------------------------------------------ */
+mg_status mg_select_magnus_steps_per_path(const mg_ops* ops2, const mg_ops* ops3,
+                                          const double* dW, int64_t P, int64_t Nf, double T,
+                                          const double* u0, int32_t K0, int32_t factor,
+                                          int32_t Kmax, double tol, int32_t precision,
+                                          int32_t* K_out, double* gap_out, int64_t* n_accepted,
+                                          void* stream);
 
 /* --------------------------------------------------------------------------
  * mg_euler_step  (eq. (EulerMaruyama))

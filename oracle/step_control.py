@@ -19,6 +19,9 @@ u2, u3 the terminal values of the iterated scheme of orders 2 and 3 with the
 same K (the same paths, eq. (MagnusFormulas) for the weights).  The first K
 with gap(K) <= tol is selected; if none qualifies the last K tried is
 returned, marked as not accepted.
+
+Per-path reading (select_steps_per_path): the same rule applied to each
+trajectory on its own, so that every path gets its own step size.
 """
 from __future__ import annotations
 
@@ -59,3 +62,32 @@ def select_steps(basis: Sequence[sp.spmatrix], dW: np.ndarray, T: float, u0: np.
         raise ValueError("K0 must divide the fine increments and not exceed Kmax")
     K, g = history[-1]
     return K, g, False, history
+
+
+def select_steps_per_path(basis: Sequence[sp.spmatrix], dW: np.ndarray, T: float,
+                          u0: np.ndarray, nx: int, nv: int, K0: int, factor: int, Kmax: int,
+                          tol: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray,
+                                              List[List[Tuple[int, float]]]]:
+    """Per path p: (K[p], gap[p], accepted[p], history[p]) of select_steps
+    run on that path alone."""
+    dW = np.atleast_2d(dW)
+    K = np.zeros(dW.shape[0], dtype=np.int64)
+    gap = np.zeros(dW.shape[0])
+    acc = np.zeros(dW.shape[0], dtype=bool)
+    hist = []
+    for p in range(dW.shape[0]):
+        K[p], gap[p], acc[p], h = select_steps(basis, dW[p:p + 1], T, u0, nx, nv, K0, factor,
+                                               Kmax, tol)
+        hist.append(h)
+    return K, gap, acc, hist
+
+
+def padded_coefficients(dW: np.ndarray, T: float, K: Sequence[int], Kmax: int,
+                        order: int) -> np.ndarray:
+    """Weights of path p with K[p] uniform steps in rows 0 .. K[p]-1 of
+    [P][Kmax][6], zero rows after them (a zero step is the identity)."""
+    dW = np.atleast_2d(dW)
+    out = np.zeros((dW.shape[0], Kmax, 6))
+    for p in range(dW.shape[0]):
+        out[p, :K[p]] = integrals.path_coefficients(dW[p:p + 1], T, int(K[p]), order)[0]
+    return out

@@ -25,6 +25,7 @@ PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_workspace_bytes", "mg_magnus_expmv", "mg_workspace_bytes_multi",
            "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_select_magnus_steps",
+           "mg_select_magnus_steps_per_path", "mg_iterated_integrals_steps",
            "mg_euler_increments",
            "mg_euler_workspace_bytes",
            "mg_euler_step",
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double),
                                            ctypes.POINTER(ctypes.c_int32), vp]
+    lib.mg_select_magnus_steps_per_path.argtypes = [vp, vp, vp, i64, i64, dbl, vp, i32, i32, i32,
+                                                    dbl, i32, vp, vp,
+                                                    ctypes.POINTER(ctypes.c_int64), vp]
+    lib.mg_iterated_integrals_steps.argtypes = [vp, i64, i64, dbl, vp, i32, i32, vp, vp, vp]
     lib.mg_autotune_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, i32,
                                       ctypes.c_char_p, sz, vp]
     lib.mg_workspace_bytes_multi.argtypes = [ctypes.POINTER(mg_job), i32]
@@ -191,6 +196,27 @@ def iterated_integrals(dW, T: float, K: int, order: int, coef=None, pathstat=Non
     return coef, pathstat
 
 
+def iterated_integrals_steps(dW, T: float, K, Kmax: int, order: int, coef=None, pathstat=None,
+                             stream=None):
+    """mg_iterated_integrals_steps: K int32 device [P] (steps of each path) ->
+    (coef [P][Kmax][6], rows beyond K[p] zero; pathstat [P][2])."""
+    import torch
+    _dev_f64(dW, "dW")
+    if not (K.is_cuda and K.dtype == torch.int32 and K.is_contiguous()):
+        raise TypeError("K must be a contiguous int32 device tensor")
+    P, Nf = dW.shape
+    if K.numel() != P:
+        raise ValueError("K needs one entry per path")
+    if coef is None:
+        coef = torch.empty((P, Kmax, 6), dtype=torch.float64, device=dW.device)
+    if pathstat is None:
+        pathstat = torch.empty((P, 2), dtype=torch.float64, device=dW.device)
+    _check(load_library().mg_iterated_integrals_steps(_ptr(dW), P, Nf, float(T), _ptr(K), int(Kmax),
+                                                      order, _ptr(coef), _ptr(pathstat),
+                                                      _stream(stream)))
+    return coef, pathstat
+
+
 def workspace_bytes(ops: Operators, P: int, K: int, precision: str = "fp64") -> int:
     return int(load_library().mg_workspace_bytes(ops.handle, P, K, PRECISIONS[precision]))
 
@@ -261,6 +287,24 @@ def select_magnus_steps(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: 
         int(Kmax), float(tol), PRECISIONS[precision], ctypes.byref(K), ctypes.byref(gap),
         ctypes.byref(acc), _stream(stream)))
     return int(K.value), float(gap.value), bool(acc.value)
+
+
+def select_magnus_steps_per_path(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: int,
+                                 factor: int = 2, Kmax: int = 1 << 20, tol: float = 1e-3,
+                                 precision: str = "fp64", stream=None):
+    """mg_select_magnus_steps_per_path: (K [P] int32, gap [P] float64, number
+    accepted) from each path's order-2/order-3 distance, dW [P][Nf]."""
+    _dev_f64(dW, "dW")
+    _dev_f64(u0, "u0")
+    P, Nf = dW.shape
+    K = np.zeros(P, dtype=np.int32)
+    gap = np.zeros(P, dtype=np.float64)
+    nacc = ctypes.c_int64(0)
+    _check(load_library().mg_select_magnus_steps_per_path(
+        ops2.handle, ops3.handle, _ptr(dW), P, Nf, float(T), _ptr(u0), int(K0), int(factor),
+        int(Kmax), float(tol), PRECISIONS[precision], K.ctypes.data, gap.ctypes.data,
+        ctypes.byref(nacc), _stream(stream)))
+    return K, gap, int(nacc.value)
 
 
 def _addr(t) -> Optional[int]:

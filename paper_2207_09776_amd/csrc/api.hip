@@ -144,6 +144,23 @@ mg_status mg_iterated_integrals(const double* dW, int64_t P, int64_t Nf, double 
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_iterated_integrals");
 }
 
+mg_status mg_iterated_integrals_steps(const double* dW, int64_t P, int64_t Nf, double T,
+                                      const int32_t* K, int32_t Kmax, int32_t order, double* coef,
+                                      double* pathstat, void* stream) {
+    g_last_error.clear();
+    const char* where = "mg_iterated_integrals_steps";
+    if (P < 0 || Kmax < 1 || Nf < 1)
+        return mg_fail(MG_ESHAPE, std::string(where) + ": need P >= 0, Kmax >= 1, Nf >= 1");
+    if (P > 0x7fffffff) return mg_fail(MG_ESHAPE, std::string(where) + ": P too large");
+    if (!(T > 0.0) || !is_finite(T)) return mg_fail(MG_EINVAL, std::string(where) + ": T must be positive");
+    if (order < 1 || order > 3) return mg_fail(MG_EINVAL, std::string(where) + ": order must be 1..3");
+    if (P == 0) return MG_OK;
+    if (!dW || !K || !coef) return mg_fail(MG_EINVAL, std::string(where) + ": NULL pointer");
+    hipError_t e = launch_iterated_integrals_steps(dW, P, Nf, T, K, Kmax, order, coef, pathstat,
+                                                   (hipStream_t)stream);
+    return e == hipSuccess ? MG_OK : hip_fail(e, where);
+}
+
 mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t NE, double* dWE,
                               void* stream) {
     g_last_error.clear();
@@ -488,6 +505,102 @@ mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const d
     *K_out = lastK;
     *gap_out = lastgap;
     *accepted = ok ? 1 : 0;
+    return MG_OK;
+}
+
+mg_status mg_select_magnus_steps_per_path(const mg_ops* ops2, const mg_ops* ops3,
+                                          const double* dW, int64_t P, int64_t Nf, double T,
+                                          const double* u0, int32_t K0, int32_t factor,
+                                          int32_t Kmax, double tol, int32_t precision,
+                                          int32_t* K_out, double* gap_out, int64_t* n_accepted,
+                                          void* stream) {
+    g_last_error.clear();
+    const std::string where = "mg_select_magnus_steps_per_path";
+    if (!ops2 || !ops3 || !dW || !u0 || !K_out || !gap_out || !n_accepted)
+        return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    if (ops2->order != 2 || ops3->order != 3)
+        return mg_fail(MG_EINVAL, where + ": need operators of orders 2 and 3");
+    const mg_grid& g2 = ops2->grid;
+    const mg_grid& g3 = ops3->grid;
+    if (g2.nx != g3.nx || g2.nv != g3.nv || g2.ax != g3.ax || g2.bx != g3.bx ||
+        g2.av != g3.av || g2.bv != g3.bv)
+        return mg_fail(MG_EINVAL, where + ": the two operators are on different grids");
+    if (P < 1 || P > 0x7fffffff || Nf < 1) return mg_fail(MG_ESHAPE, where + ": bad sizes");
+    if (K0 < 1 || factor < 2 || Kmax < K0 || Nf % K0 != 0)
+        return mg_fail(MG_EINVAL, where + ": need K0 >= 1 dividing Nf, factor >= 2, Kmax >= K0");
+    if (!(tol > 0.0) || !is_finite(T) || !(T > 0.0))
+        return mg_fail(MG_EINVAL, where + ": need tol > 0 and T > 0");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t N = (size_t)g2.nx * g2.nv;
+    int64_t Kcap = K0;
+    while (Kcap * factor <= Kmax && Nf % (Kcap * factor) == 0) Kcap *= factor;
+    const size_t ws2 = mg_workspace_bytes(ops2, P, (int32_t)Kcap, precision);
+    const size_t ws3 = mg_workspace_bytes(ops3, P, (int32_t)Kcap, precision);
+    if (ws2 == 0 || ws3 == 0)
+        return mg_fail(MG_EUNSUPPORTED, where + ": no kernel for this grid and precision");
+    const size_t wsb = std::max(ws2, ws3);
+    double *coef = nullptr, *u2 = nullptr, *u3 = nullptr, *err = nullptr;
+    int32_t* fl = nullptr;
+    void* ws = nullptr;
+    auto cleanup = [&] {
+        for (void* q : {(void*)coef, (void*)u2, (void*)u3, (void*)err, (void*)fl, ws})
+            if (q) (void)hipFree(q);
+    };
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc((void**)&coef, (size_t)P * Kcap * 6 * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&u2, (size_t)P * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&u3, (size_t)P * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&err, (size_t)P * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&fl, (size_t)P * 2 * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&ws, wsb)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, where.c_str());
+    }
+    std::vector<double> herr((size_t)P);
+    std::vector<int32_t> hfl((size_t)P * 2);
+    std::vector<char> done((size_t)P, 0);
+    int64_t nacc = 0;
+    mg_status st = MG_OK;
+    int32_t K = K0;
+    // every path runs each rung of the ladder until all are accepted (the
+    // rungs are batch launches; a path keeps the first step count whose
+    // order-2/order-3 distance is within tol)
+    while (K <= Kmax && Nf % K == 0 && nacc < P) {
+        if ((st = mg_iterated_integrals(dW, P, Nf, T, K, 3, coef, nullptr, stream)) != MG_OK) break;
+        if ((st = mg_magnus_expmv(ops2, coef, P, K, u0, 1, u2, precision, 0.0, ws, wsb, nullptr,
+                                  fl, stream)) != MG_OK)
+            break;
+        if ((st = mg_magnus_expmv(ops3, coef, P, K, u0, 1, u3, precision, 0.0, ws, wsb, nullptr,
+                                  fl + P, stream)) != MG_OK)
+            break;
+        if ((st = mg_error_vs_exact(&g2, nullptr, nullptr, u2, u3, P, 0, err, stream)) != MG_OK)
+            break;
+        if ((e = hipMemcpyAsync(herr.data(), err, (size_t)P * sizeof(double),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(hfl.data(), fl, (size_t)P * 2 * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess) {
+            st = hip_fail(e, where.c_str());
+            break;
+        }
+        for (int64_t p = 0; p < P; ++p) {
+            if (done[p]) continue;
+            const double gap = (hfl[p] || hfl[P + p] || !std::isfinite(herr[p]))
+                                   ? std::numeric_limits<double>::infinity()
+                                   : herr[p];
+            K_out[p] = K;
+            gap_out[p] = gap;
+            if (gap <= tol) {
+                done[p] = 1;
+                ++nacc;
+            }
+        }
+        if ((int64_t)K * factor > 0x7fffffff) break;
+        K *= factor;
+    }
+    cleanup();
+    if (st != MG_OK) return st;
+    *n_accepted = nacc;
     return MG_OK;
 }
 

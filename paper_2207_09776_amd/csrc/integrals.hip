@@ -1,7 +1,8 @@
 // Lebesgue integrals of the fine Brownian path per Magnus step and the
 // weights of eq. (MagnusFormulas).
 //
-// One workgroup per path walks its K sub-intervals in order.  On sub-interval
+// One workgroup per path walks its K sub-intervals in order (K the same for
+// every path, or one count per path with the rows beyond it zero).  On sub-interval
 // k the path restarts (W~_0 = 0) and the integrals int W~, int W~^2,
 // int r W~ dr are taken exactly for the piecewise-linear path through the fine
 // nodes r_i = i delta:
@@ -30,13 +31,23 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
+// Kp (nullable): steps of each path; path p then fills rows 0 .. Kp[p]-1 of
+// its Kstride rows and zeros the rest (a zero step is the identity), or fills
+// every row with NaN when Kp[p] is not a divisor of Nf in 1 .. Kstride.
 __global__ __launch_bounds__(kThreads) void iterated_integrals_kernel(
-    const double* __restrict__ dW, int64_t Nf, double T, int K, int order,
-    double* __restrict__ coef, double* __restrict__ pathstat) {
+    const double* __restrict__ dW, int64_t Nf, double T, int Kuni, const int32_t* __restrict__ Kp,
+    int Kstride, int order, double* __restrict__ coef, double* __restrict__ pathstat) {
     __shared__ double scan[kThreads];
     __shared__ double red[kThreads / 64];
     const int64_t p = blockIdx.x;
     const int t = threadIdx.x;
+    const int K = Kp ? Kp[p] : Kuni;
+    if (K < 1 || K > Kstride || Nf % K != 0) {
+        for (int i = t; i < Kstride * 6; i += kThreads) coef[p * Kstride * 6 + i] = NAN;
+        if (t == 0 && pathstat) pathstat[2 * p] = pathstat[2 * p + 1] = NAN;
+        return;
+    }
+    for (int i = K * 6 + t; i < Kstride * 6; i += kThreads) coef[p * Kstride * 6 + i] = 0.0;
     const int64_t n = Nf / K;
     const double h = T / K;
     const double delta = T / (double)Nf;
@@ -77,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void iterated_integrals_kernel(
         const double J = block_sum(sj, red) * (delta / 6.0);
         const double DW = total;
         if (t == 0) {
-            double* c = coef + ((int64_t)p * K + k) * 6;
+            double* c = coef + ((int64_t)p * Kstride + k) * 6;
             c[0] = h;
             c[1] = DW;
             c[2] = order >= 2 ? -0.5 * h : 0.0;
@@ -121,6 +132,14 @@ hipError_t launch_euler_increments(const double* dW, int64_t P, int64_t Nf, int 
 hipError_t launch_iterated_integrals(const double* dW, int64_t P, int64_t Nf, double T, int K,
                                      int order, double* coef, double* pathstat, hipStream_t s) {
     hipLaunchKernelGGL(iterated_integrals_kernel, dim3((unsigned)P), dim3(kThreads), 0, s, dW, Nf,
-                       T, K, order, coef, pathstat);
+                       T, K, (const int32_t*)nullptr, K, order, coef, pathstat);
+    return hipGetLastError();
+}
+
+hipError_t launch_iterated_integrals_steps(const double* dW, int64_t P, int64_t Nf, double T,
+                                           const int32_t* Kp, int Kmax, int order, double* coef,
+                                           double* pathstat, hipStream_t s) {
+    hipLaunchKernelGGL(iterated_integrals_kernel, dim3((unsigned)P), dim3(kThreads), 0, s, dW, Nf,
+                       T, Kmax, Kp, Kmax, order, coef, pathstat);
     return hipGetLastError();
 }

@@ -69,6 +69,9 @@ mg_status mg_fail(mg_status code, const std::string& msg);
 // kernel launchers (defined next to the kernels)
 hipError_t launch_iterated_integrals(const double* dW, int64_t P, int64_t Nf, double T, int K,
                                      int order, double* coef, double* pathstat, hipStream_t s);
+hipError_t launch_iterated_integrals_steps(const double* dW, int64_t P, int64_t Nf, double T,
+                                           const int32_t* Kp, int Kmax, int order, double* coef,
+                                           double* pathstat, hipStream_t s);
 hipError_t launch_euler_increments(const double* dW, int64_t P, int64_t Nf, int NE, double* dWE,
                                    hipStream_t s);
 hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int K, double tol,
