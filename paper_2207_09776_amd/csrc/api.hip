@@ -408,6 +408,107 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
     return MG_OK;
 }
 
+namespace {
+
+// The ladder shared by the two step-size selections: argument checks, the
+// device buffers of a set-up call, and one rung (both orders over the paths
+// at K steps, their relative distances and flags copied to the host).
+struct StepLadder {
+    const mg_ops *ops2, *ops3;
+    const double *dW, *u0;
+    int64_t P, Nf;
+    double T;
+    int32_t precision;
+    void* stream;
+    size_t N = 0, wsb = 0;
+    double *coef = nullptr, *u2 = nullptr, *u3 = nullptr, *err = nullptr;
+    int32_t* fl = nullptr;
+    void* ws = nullptr;
+    std::vector<double> herr;
+    std::vector<int32_t> hfl;
+
+    ~StepLadder() {
+        for (void* q : {(void*)coef, (void*)u2, (void*)u3, (void*)err, (void*)fl, ws})
+            if (q) (void)hipFree(q);
+    }
+
+    mg_status check(const std::string& where, int32_t K0, int32_t factor, int32_t Kmax,
+                    double tol) const {
+        if (!ops2 || !ops3 || !dW || !u0) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+        if (ops2->order != 2 || ops3->order != 3)
+            return mg_fail(MG_EINVAL, where + ": need operators of orders 2 and 3");
+        const mg_grid& g2 = ops2->grid;
+        const mg_grid& g3 = ops3->grid;
+        if (g2.nx != g3.nx || g2.nv != g3.nv || g2.ax != g3.ax || g2.bx != g3.bx ||
+            g2.av != g3.av || g2.bv != g3.bv)
+            return mg_fail(MG_EINVAL, where + ": the two operators are on different grids");
+        if (P < 1 || P > 0x7fffffff || Nf < 1) return mg_fail(MG_ESHAPE, where + ": bad sizes");
+        if (K0 < 1 || factor < 2 || Kmax < K0 || Nf % K0 != 0)
+            return mg_fail(MG_EINVAL,
+                           where + ": need K0 >= 1 dividing Nf, factor >= 2, Kmax >= K0");
+        if (!(tol > 0.0) || !is_finite(T) || !(T > 0.0))
+            return mg_fail(MG_EINVAL, where + ": need tol > 0 and T > 0");
+        return MG_OK;
+    }
+
+    // buffers sized for the largest K the ladder may reach
+    mg_status allocate(const std::string& where, int32_t K0, int32_t factor, int32_t Kmax) {
+        N = (size_t)ops2->grid.nx * ops2->grid.nv;
+        int64_t Kcap = K0;
+        while (Kcap * factor <= Kmax && Nf % (Kcap * factor) == 0) Kcap *= factor;
+        const size_t ws2 = mg_workspace_bytes(ops2, P, (int32_t)Kcap, precision);
+        const size_t ws3 = mg_workspace_bytes(ops3, P, (int32_t)Kcap, precision);
+        if (ws2 == 0 || ws3 == 0)
+            return mg_fail(MG_EUNSUPPORTED, where + ": no kernel for this grid and precision");
+        wsb = std::max(ws2, ws3);
+        hipError_t e = hipSuccess;
+        if ((e = hipMalloc((void**)&coef, (size_t)P * Kcap * 6 * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void**)&u2, (size_t)P * N * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void**)&u3, (size_t)P * N * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void**)&err, (size_t)P * sizeof(double))) != hipSuccess ||
+            (e = hipMalloc((void**)&fl, (size_t)P * 2 * sizeof(int32_t))) != hipSuccess ||
+            (e = hipMalloc(&ws, wsb)) != hipSuccess)
+            return hip_fail(e, where.c_str());
+        herr.assign((size_t)P, 0.0);
+        hfl.assign((size_t)P * 2, 0);
+        return MG_OK;
+    }
+
+    // one rung: gap(p) = ||u3_p - u2_p||_F / ||u3_p||_F at K steps, +inf for a
+    // flagged or non-finite path
+    mg_status rung(const std::string& where, int32_t K, std::vector<double>& gap) {
+        mg_status st;
+        if ((st = mg_iterated_integrals(dW, P, Nf, T, K, 3, coef, nullptr, stream)) != MG_OK)
+            return st;
+        // the order-3 weights: their first four are the order-2 ones
+        if ((st = mg_magnus_expmv(ops2, coef, P, K, u0, 1, u2, precision, 0.0, ws, wsb, nullptr,
+                                  fl, stream)) != MG_OK)
+            return st;
+        if ((st = mg_magnus_expmv(ops3, coef, P, K, u0, 1, u3, precision, 0.0, ws, wsb, nullptr,
+                                  fl + P, stream)) != MG_OK)
+            return st;
+        if ((st = mg_error_vs_exact(&ops2->grid, nullptr, nullptr, u2, u3, P, 0, err, stream)) !=
+            MG_OK)
+            return st;
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e = hipSuccess;
+        if ((e = hipMemcpyAsync(herr.data(), err, (size_t)P * sizeof(double),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipMemcpyAsync(hfl.data(), fl, (size_t)P * 2 * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, where.c_str());
+        gap.resize((size_t)P);
+        for (int64_t p = 0; p < P; ++p)
+            gap[p] = (hfl[p] || hfl[P + p] || !std::isfinite(herr[p]))
+                         ? std::numeric_limits<double>::infinity()
+                         : herr[p];
+        return MG_OK;
+    }
+};
+
+}  // namespace
+
 mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const double* dW,
                                  int64_t Ps, int64_t Nf, double T, const double* u0, int32_t K0,
                                  int32_t factor, int32_t Kmax, double tol, int32_t precision,
@@ -415,82 +516,19 @@ mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const d
                                  void* stream) {
     g_last_error.clear();
     const std::string where = "mg_select_magnus_steps";
-    if (!ops2 || !ops3 || !dW || !u0 || !K_out || !gap_out || !accepted)
-        return mg_fail(MG_EINVAL, where + ": NULL pointer");
-    if (ops2->order != 2 || ops3->order != 3)
-        return mg_fail(MG_EINVAL, where + ": need operators of orders 2 and 3");
-    const mg_grid& g2 = ops2->grid;
-    const mg_grid& g3 = ops3->grid;
-    if (g2.nx != g3.nx || g2.nv != g3.nv || g2.ax != g3.ax || g2.bx != g3.bx ||
-        g2.av != g3.av || g2.bv != g3.bv)
-        return mg_fail(MG_EINVAL, where + ": the two operators are on different grids");
-    if (Ps < 1 || Ps > 0x7fffffff || Nf < 1) return mg_fail(MG_ESHAPE, where + ": bad sizes");
-    if (K0 < 1 || factor < 2 || Kmax < K0 || Nf % K0 != 0)
-        return mg_fail(MG_EINVAL, where + ": need K0 >= 1 dividing Nf, factor >= 2, Kmax >= K0");
-    if (!(tol > 0.0) || !is_finite(T) || !(T > 0.0))
-        return mg_fail(MG_EINVAL, where + ": need tol > 0 and T > 0");
-    hipStream_t s = (hipStream_t)stream;
-    const size_t N = (size_t)g2.nx * g2.nv;
-    // set-up call: its own device buffers, sized for the largest K it may try
-    int64_t Kcap = K0;
-    while (Kcap * factor <= Kmax && Nf % (Kcap * factor) == 0) Kcap *= factor;
-    const size_t ws2 = mg_workspace_bytes(ops2, Ps, (int32_t)Kcap, precision);
-    const size_t ws3 = mg_workspace_bytes(ops3, Ps, (int32_t)Kcap, precision);
-    if (ws2 == 0 || ws3 == 0)
-        return mg_fail(MG_EUNSUPPORTED, where + ": no kernel for this grid and precision");
-    const size_t wsb = std::max(ws2, ws3);
-    double *coef = nullptr, *ps = nullptr, *u2 = nullptr, *u3 = nullptr, *err = nullptr;
-    int32_t* fl = nullptr;
-    void* ws = nullptr;
-    auto cleanup = [&] {
-        for (void* q : {(void*)coef, (void*)ps, (void*)u2, (void*)u3, (void*)err, (void*)fl, ws})
-            if (q) (void)hipFree(q);
-    };
-    hipError_t e = hipSuccess;
-    if ((e = hipMalloc((void**)&coef, (size_t)Ps * Kcap * 6 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&ps, (size_t)Ps * 2 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&u2, (size_t)Ps * N * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&u3, (size_t)Ps * N * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&err, (size_t)Ps * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&fl, (size_t)Ps * 2 * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&ws, wsb)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, where.c_str());
-    }
-    std::vector<double> herr((size_t)Ps);
-    std::vector<int32_t> hfl((size_t)Ps * 2);
-    mg_status st = MG_OK;
+    if (!K_out || !gap_out || !accepted) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    StepLadder L{ops2, ops3, dW, u0, Ps, Nf, T, precision, stream};
+    mg_status st = L.check(where, K0, factor, Kmax, tol);
+    if (st != MG_OK || (st = L.allocate(where, K0, factor, Kmax)) != MG_OK) return st;
+    std::vector<double> gaps;
     int32_t K = K0, lastK = 0;
     double lastgap = 0.0;
     bool ok = false;
     while (K <= Kmax && Nf % K == 0) {
-        // the order-3 weights (their first four are the order-2 ones)
-        if ((st = mg_iterated_integrals(dW, Ps, Nf, T, K, 3, coef, ps, stream)) != MG_OK) break;
-        if ((st = mg_magnus_expmv(ops2, coef, Ps, K, u0, 1, u2, precision, 0.0, ws, wsb, nullptr,
-                                  fl, stream)) != MG_OK)
-            break;
-        if ((st = mg_magnus_expmv(ops3, coef, Ps, K, u0, 1, u3, precision, 0.0, ws, wsb, nullptr,
-                                  fl + Ps, stream)) != MG_OK)
-            break;
-        if ((st = mg_error_vs_exact(&g2, nullptr, nullptr, u2, u3, Ps, 0, err, stream)) != MG_OK)
-            break;
-        if ((e = hipMemcpyAsync(herr.data(), err, (size_t)Ps * sizeof(double),
-                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(hfl.data(), fl, (size_t)Ps * 2 * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess) {
-            st = hip_fail(e, where.c_str());
-            break;
-        }
-        // the largest relative distance over the sample; a flagged or
-        // non-finite path counts as an infinite distance
+        if ((st = L.rung(where, K, gaps)) != MG_OK) return st;
+        // the largest distance over the sample decides
         double gap = 0.0;
-        for (int64_t p = 0; p < Ps; ++p) {
-            const double v = (hfl[p] || hfl[Ps + p] || !std::isfinite(herr[p]))
-                                 ? std::numeric_limits<double>::infinity()
-                                 : herr[p];
-            gap = std::max(gap, v);
-        }
+        for (double g : gaps) gap = std::max(gap, g);
         lastK = K;
         lastgap = gap;
         if (gap <= tol) {
@@ -500,8 +538,6 @@ mg_status mg_select_magnus_steps(const mg_ops* ops2, const mg_ops* ops3, const d
         if ((int64_t)K * factor > 0x7fffffff) break;
         K *= factor;
     }
-    cleanup();
-    if (st != MG_OK) return st;
     *K_out = lastK;
     *gap_out = lastgap;
     *accepted = ok ? 1 : 0;
@@ -516,81 +552,23 @@ mg_status mg_select_magnus_steps_per_path(const mg_ops* ops2, const mg_ops* ops3
                                           void* stream) {
     g_last_error.clear();
     const std::string where = "mg_select_magnus_steps_per_path";
-    if (!ops2 || !ops3 || !dW || !u0 || !K_out || !gap_out || !n_accepted)
-        return mg_fail(MG_EINVAL, where + ": NULL pointer");
-    if (ops2->order != 2 || ops3->order != 3)
-        return mg_fail(MG_EINVAL, where + ": need operators of orders 2 and 3");
-    const mg_grid& g2 = ops2->grid;
-    const mg_grid& g3 = ops3->grid;
-    if (g2.nx != g3.nx || g2.nv != g3.nv || g2.ax != g3.ax || g2.bx != g3.bx ||
-        g2.av != g3.av || g2.bv != g3.bv)
-        return mg_fail(MG_EINVAL, where + ": the two operators are on different grids");
-    if (P < 1 || P > 0x7fffffff || Nf < 1) return mg_fail(MG_ESHAPE, where + ": bad sizes");
-    if (K0 < 1 || factor < 2 || Kmax < K0 || Nf % K0 != 0)
-        return mg_fail(MG_EINVAL, where + ": need K0 >= 1 dividing Nf, factor >= 2, Kmax >= K0");
-    if (!(tol > 0.0) || !is_finite(T) || !(T > 0.0))
-        return mg_fail(MG_EINVAL, where + ": need tol > 0 and T > 0");
-    hipStream_t s = (hipStream_t)stream;
-    const size_t N = (size_t)g2.nx * g2.nv;
-    int64_t Kcap = K0;
-    while (Kcap * factor <= Kmax && Nf % (Kcap * factor) == 0) Kcap *= factor;
-    const size_t ws2 = mg_workspace_bytes(ops2, P, (int32_t)Kcap, precision);
-    const size_t ws3 = mg_workspace_bytes(ops3, P, (int32_t)Kcap, precision);
-    if (ws2 == 0 || ws3 == 0)
-        return mg_fail(MG_EUNSUPPORTED, where + ": no kernel for this grid and precision");
-    const size_t wsb = std::max(ws2, ws3);
-    double *coef = nullptr, *u2 = nullptr, *u3 = nullptr, *err = nullptr;
-    int32_t* fl = nullptr;
-    void* ws = nullptr;
-    auto cleanup = [&] {
-        for (void* q : {(void*)coef, (void*)u2, (void*)u3, (void*)err, (void*)fl, ws})
-            if (q) (void)hipFree(q);
-    };
-    hipError_t e = hipSuccess;
-    if ((e = hipMalloc((void**)&coef, (size_t)P * Kcap * 6 * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&u2, (size_t)P * N * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&u3, (size_t)P * N * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&err, (size_t)P * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc((void**)&fl, (size_t)P * 2 * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&ws, wsb)) != hipSuccess) {
-        cleanup();
-        return hip_fail(e, where.c_str());
-    }
-    std::vector<double> herr((size_t)P);
-    std::vector<int32_t> hfl((size_t)P * 2);
+    if (!K_out || !gap_out || !n_accepted) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    StepLadder L{ops2, ops3, dW, u0, P, Nf, T, precision, stream};
+    mg_status st = L.check(where, K0, factor, Kmax, tol);
+    if (st != MG_OK || (st = L.allocate(where, K0, factor, Kmax)) != MG_OK) return st;
+    std::vector<double> gaps;
     std::vector<char> done((size_t)P, 0);
     int64_t nacc = 0;
-    mg_status st = MG_OK;
     int32_t K = K0;
-    // every path runs each rung of the ladder until all are accepted (the
-    // rungs are batch launches; a path keeps the first step count whose
-    // order-2/order-3 distance is within tol)
+    // every rung runs as one batch over the paths until all are accepted; a
+    // path keeps the first step count whose distance is within tol
     while (K <= Kmax && Nf % K == 0 && nacc < P) {
-        if ((st = mg_iterated_integrals(dW, P, Nf, T, K, 3, coef, nullptr, stream)) != MG_OK) break;
-        if ((st = mg_magnus_expmv(ops2, coef, P, K, u0, 1, u2, precision, 0.0, ws, wsb, nullptr,
-                                  fl, stream)) != MG_OK)
-            break;
-        if ((st = mg_magnus_expmv(ops3, coef, P, K, u0, 1, u3, precision, 0.0, ws, wsb, nullptr,
-                                  fl + P, stream)) != MG_OK)
-            break;
-        if ((st = mg_error_vs_exact(&g2, nullptr, nullptr, u2, u3, P, 0, err, stream)) != MG_OK)
-            break;
-        if ((e = hipMemcpyAsync(herr.data(), err, (size_t)P * sizeof(double),
-                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipMemcpyAsync(hfl.data(), fl, (size_t)P * 2 * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, s)) != hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess) {
-            st = hip_fail(e, where.c_str());
-            break;
-        }
+        if ((st = L.rung(where, K, gaps)) != MG_OK) return st;
         for (int64_t p = 0; p < P; ++p) {
             if (done[p]) continue;
-            const double gap = (hfl[p] || hfl[P + p] || !std::isfinite(herr[p]))
-                                   ? std::numeric_limits<double>::infinity()
-                                   : herr[p];
             K_out[p] = K;
-            gap_out[p] = gap;
-            if (gap <= tol) {
+            gap_out[p] = gaps[p];
+            if (gaps[p] <= tol) {
                 done[p] = 1;
                 ++nacc;
             }
@@ -598,8 +576,6 @@ mg_status mg_select_magnus_steps_per_path(const mg_ops* ops2, const mg_ops* ops3
         if ((int64_t)K * factor > 0x7fffffff) break;
         K *= factor;
     }
-    cleanup();
-    if (st != MG_OK) return st;
     *n_accepted = nacc;
     return MG_OK;
 }
