@@ -729,6 +729,13 @@ def main():
                             "gap": gap, "accepted": acc, "workload_K": K,
                             "seconds": time.perf_counter() - t0}
             log(f"step control: K = {Ksel} (gap {gap:.3e}, accepted {acc}); workload K = {K}")
+            # the same rule per path on the same sample: each path's own count
+            Kp, gp, nacc = mg.select_magnus_steps_per_path(o2, o3, dW[:Ps].contiguous(), w.T, u0,
+                                                           K0=4, factor=2, Kmax=w.Nf, tol=1e-3)
+            counts = {int(k): int((Kp == k).sum()) for k in sorted(set(Kp.tolist()))}
+            step_control["per_path"] = {"K_counts": counts, "accepted": nacc,
+                                        "max_gap": float(gp.max())}
+            log(f"step control per path: K counts {counts}, {nacc} of {Ps} accepted")
         except mg.MagnusError as ex:
             step_control = {"unsupported": str(ex)}
 
