@@ -43,11 +43,13 @@ __global__ __launch_bounds__(kThreads) void iterated_integrals_kernel(
     const int t = threadIdx.x;
     const int K = Kp ? Kp[p] : Kuni;
     if (K < 1 || K > Kstride || Nf % K != 0) {
-        for (int i = t; i < Kstride * 6; i += kThreads) coef[p * Kstride * 6 + i] = NAN;
+        for (int64_t i = t; i < (int64_t)Kstride * 6; i += kThreads)
+            coef[p * Kstride * 6 + i] = NAN;
         if (t == 0 && pathstat) pathstat[2 * p] = pathstat[2 * p + 1] = NAN;
         return;
     }
-    for (int i = K * 6 + t; i < Kstride * 6; i += kThreads) coef[p * Kstride * 6 + i] = 0.0;
+    for (int64_t i = (int64_t)K * 6 + t; i < (int64_t)Kstride * 6; i += kThreads)
+        coef[p * Kstride * 6 + i] = 0.0;
     const int64_t n = Nf / K;
     const double h = T / K;
     const double delta = T / (double)Nf;
