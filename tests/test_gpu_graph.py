@@ -127,3 +127,44 @@ def test_graph_replays_cooperative_and_multi_job():
         u2, fl, _ = mg.magnus_expmv(b0["ops"], b0["coef"], b0["u0"], precision="fp32c")
         torch.cuda.synchronize()
         assert int(fl.abs().sum()) == 0
+
+
+def test_graph_replays_per_path_step_counts():
+    """The per-path batch (weights with a step count per path, zero steps
+    after it, one Taylor launch at K = Kmax) captured in a graph: every
+    replay equals the eager result bit for bit, on a resident and a
+    cooperative grid."""
+    print("graph replay per-path step counts", flush=True)
+    P, Nf, Kmax = 4, 256, 16
+    Kp = torch.tensor([4, 16, 2, 8], dtype=torch.int32, device=DEV)
+    dW = torch.from_numpy(wl.brownian_increments(53, P, Nf)).to(DEV)
+    c = wl.langevin_constant(1.0, 0.5)
+    for n, prec, T in ((48, "fp64", 1.0), (160, "fp32c", 0.05)):
+        ops = mg.build_operators(n, n, -4, 4, -4, 4, wl.sample_coefficients(c, n, n, -4, 4, -4, 4), 2)
+        u0 = torch.from_numpy(wl.gaussian_density(n, n, -4, 4, -4, 4, 0.25).reshape(-1)).to(DEV)
+        coef = torch.empty((P, Kmax, 6), dtype=torch.float64, device=DEV)
+        ps = torch.empty((P, 2), dtype=torch.float64, device=DEV)
+        uT = torch.empty((P, n * n), dtype=torch.float64, device=DEV)
+        ws = torch.empty(mg.workspace_bytes(ops, P, Kmax, prec), dtype=torch.uint8, device=DEV)
+
+        def step():
+            mg.iterated_integrals_steps(dW, T, Kp, Kmax, 2, coef=coef, pathstat=ps)
+            mg.magnus_expmv(ops, coef, u0, precision=prec, uT=uT, ws=ws)
+
+        step()
+        torch.cuda.synchronize()
+        want = uT.clone()
+        assert bool(torch.isfinite(want).all())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for r in range(3):
+            uT.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(uT, want), (n, r)
+            # eager work between replays
+            cf, _ = mg.iterated_integrals(dW, T, 4, 2)
+            _, fl, _ = mg.magnus_expmv(ops, cf, u0, precision=prec)
+            torch.cuda.synchronize()
+            assert int(fl.abs().sum()) == 0
