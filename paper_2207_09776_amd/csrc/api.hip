@@ -431,6 +431,8 @@ struct StepLadder {
         for (void* q : {(void*)coef, (void*)u2, (void*)u3, (void*)err, (void*)fl, ws})
             if (q) (void)hipFree(q);
     }
+    StepLadder(const StepLadder&) = delete;              // owns its device buffers
+    StepLadder& operator=(const StepLadder&) = delete;
 
     mg_status check(const std::string& where, int32_t K0, int32_t factor, int32_t Kmax,
                     double tol) const {
