@@ -48,6 +48,7 @@ typedef int32_t mg_status;
 #define MG_EUNSUPPORTED (-3)   /* valid input this build does not implement  */
 #define MG_EHIP         (-4)   /* HIP runtime error                          */
 #define MG_ENOMEM       (-5)   /* host allocation failed / workspace too small */
+#define MG_ENONFINITE   (-6)   /* mg_check_flags: at least one path is flagged  */
 
 /* Per-path flag bits written to `flags[p]` (0 = path finished normally). */
 #define MG_FLAG_NONFINITE 1    /* a NaN or Inf appeared in the path's state   */
@@ -357,6 +358,25 @@ mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* d
 mg_status mg_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const double* pathstat,
                             const double* u, const double* uref, int64_t P, int32_t kappa,
                             double* err, void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_check_flags  (per-path failure report of the asynchronous calls)
+ *
+ * The compute calls are asynchronous, so a non-finite or out-of-range path
+ * cannot change their return value; it sets bits in their `flags` array.
+ * This call waits for `stream`, reads the P flags and returns MG_ENONFINITE
+ * when any path has a bit set (mg_last_error gives the number of flagged
+ * paths and the first one), MG_OK otherwise.
+ *   flags    : device int32 [P], as written by mg_magnus_expmv,
+ *              mg_magnus_expmv_multi or mg_euler_step.
+ *   bits_out : host, the OR of all flags (may be NULL).
+ *   first_out: host, the first flagged path or -1 (may be NULL).
+ * A synchronous check (it waits for the stream); it allocates host memory
+ * only.  Errors: MG_EINVAL (NULL flags with P > 0), MG_ESHAPE (P < 0),
+ * MG_EHIP, MG_ENOMEM.
+ * ------------------------------------------------------------------------ */
+mg_status mg_check_flags(const int32_t* flags, int64_t P, int32_t* bits_out, int64_t* first_out,
+                         void* stream);
 
 /* Message describing the last failing call on this thread ("" if none). */
 const char* mg_last_error(void);

@@ -8,8 +8,10 @@ without a GPU; calling a compute function needs the built library
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
+import sys
 from typing import Dict, Optional
 
 import numpy as np
@@ -18,6 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmagnus.so")
 
 MG_OK, MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP, MG_ENOMEM = 0, -1, -2, -3, -4, -5
+MG_ENONFINITE = -6
 MG_FLAG_NONFINITE, MG_FLAG_NORM, MG_FLAG_ABORT = 1, 2, 4
 MG_FP64, MG_FP32C = 0, 1
 PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
@@ -29,7 +32,7 @@ EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_euler_increments",
            "mg_euler_workspace_bytes",
            "mg_euler_step",
-           "mg_error_vs_exact",
+           "mg_error_vs_exact", "mg_check_flags",
            "mg_last_error", "mg_timing_enable", "mg_timing_read", "mg_timing_reset", "mg_version")
 
 
@@ -99,13 +102,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_euler_increments.argtypes = [vp, i64, i64, i32, vp, vp]
     lib.mg_error_vs_exact.argtypes = [ctypes.POINTER(mg_grid), ctypes.POINTER(mg_exact), vp, vp,
                                       vp, i64, i32, vp, vp]
+    lib.mg_check_flags.argtypes = [vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i64), vp]
     lib.mg_last_error.restype = ctypes.c_char_p
     lib.mg_version.restype = ctypes.c_char_p
     lib.mg_timing_enable.argtypes = [i32]
     lib.mg_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
                  "mg_magnus_expmv", "mg_magnus_expmv_multi", "mg_euler_increments",
-                 "mg_euler_step", "mg_error_vs_exact", "mg_timing_enable",
+                 "mg_euler_step", "mg_error_vs_exact", "mg_check_flags", "mg_timing_enable",
                  "mg_timing_read", "mg_timing_reset"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -128,6 +132,34 @@ def _stream(stream=None):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _stream_scoped(fn):
+    """Runs a binding function with the caller's stream current (see _on)."""
+    import functools
+    import inspect
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kwargs):
+        stream = sig.bind(*args, **kwargs).arguments.get("stream")
+        with _on(stream):
+            return fn(*args, **kwargs)
+    return wrapper
+
+
+@contextlib.contextmanager
+def _on(stream):
+    """Allocate the call's temporaries (workspace, flags, statistics) on the
+    stream the library runs on: the caching allocator then reuses them only
+    after the work queued there, and their zero fill is ordered before the
+    kernels that write them."""
+    if stream is None:
+        yield
+        return
+    import torch
+    with torch.cuda.stream(stream):
+        yield
 
 
 def _dev_f64(t, name):
@@ -167,11 +199,24 @@ class Operators:
         return self._h
 
     def close(self):
+        """Free the library's tables now (the handle is unusable afterwards).
+        The caller makes sure no queued work still uses them."""
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().mg_free_operators(self._h)
             self._h = None
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
     def __del__(self):
+        # No HIP call while the interpreter shuts down: the HIP runtime and the
+        # profiler's interception may already be gone then; the process exit
+        # releases the device memory.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -182,6 +227,7 @@ def build_operators(nx, nv, ax, bx, av, bv, coeffs, order) -> Operators:
     return Operators(nx, nv, ax, bx, av, bv, coeffs, order)
 
 
+@_stream_scoped
 def iterated_integrals(dW, T: float, K: int, order: int, coef=None, pathstat=None, stream=None):
     """mg_iterated_integrals: dW [P][Nf] float64 CUDA -> (coef [P][K][6], pathstat [P][2])."""
     import torch
@@ -196,6 +242,7 @@ def iterated_integrals(dW, T: float, K: int, order: int, coef=None, pathstat=Non
     return coef, pathstat
 
 
+@_stream_scoped
 def iterated_integrals_steps(dW, T: float, K, Kmax: int, order: int, coef=None, pathstat=None,
                              stream=None):
     """mg_iterated_integrals_steps: K int32 device [P] (steps of each path) ->
@@ -221,6 +268,7 @@ def workspace_bytes(ops: Operators, P: int, K: int, precision: str = "fp64") -> 
     return int(load_library().mg_workspace_bytes(ops.handle, P, K, PRECISIONS[precision]))
 
 
+@_stream_scoped
 def magnus_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float = 0.0,
                  uT=None, ws=None, want_stats: bool = False, stream=None):
     """mg_magnus_expmv.  u0: [N] (shared) or [P][N].  Returns (uT, flags, stats)."""
@@ -246,6 +294,7 @@ def magnus_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float =
     return uT, flags, stats
 
 
+@_stream_scoped
 def autotune_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float = 0.0,
                    uT=None, ws=None, reps: int = 3, stream=None) -> str:
     """mg_autotune_expmv: times the kernel shapes for this grid on the batch and
@@ -271,6 +320,7 @@ def autotune_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float
     return buf.value.decode()
 
 
+@_stream_scoped
 def select_magnus_steps(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: int,
                         factor: int = 2, Kmax: int = 1 << 20, tol: float = 1e-3,
                         precision: str = "fp64", stream=None):
@@ -289,6 +339,7 @@ def select_magnus_steps(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: 
     return int(K.value), float(gap.value), bool(acc.value)
 
 
+@_stream_scoped
 def select_magnus_steps_per_path(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: int,
                                  factor: int = 2, Kmax: int = 1 << 20, tol: float = 1e-3,
                                  precision: str = "fp64", stream=None):
@@ -320,6 +371,7 @@ def _job_array(jobs):
     return arr
 
 
+@_stream_scoped
 def magnus_expmv_multi(jobs, ws=None, stream=None):
     """mg_magnus_expmv_multi.  Each job is a dict with ops, coef [P][K][6], u0
     ([N] or [P][N]), and optionally precision, tol, uT, want_stats; returns a
@@ -353,6 +405,7 @@ def magnus_expmv_multi(jobs, ws=None, stream=None):
     return [(j["uT"], j["flags"], j["stats"]) for j in prepared]
 
 
+@_stream_scoped
 def euler_increments(dW, NE: int, dWE=None, stream=None):
     """mg_euler_increments: [P][Nf] fine increments -> [P][NE] Euler increments."""
     import torch
@@ -372,6 +425,7 @@ def euler_workspace_bytes(ops: Operators, P: int) -> int:
     return n
 
 
+@_stream_scoped
 def euler_step(ops: Operators, u, dWE, dt: float, ws=None, stream=None):
     """mg_euler_step: NE Euler-Maruyama steps in place on u [P][N]; returns flags."""
     import torch
@@ -389,6 +443,7 @@ def euler_step(ops: Operators, u, dWE, dt: float, ws=None, stream=None):
     return flags
 
 
+@_stream_scoped
 def error_vs_exact(ops_or_grid, u, pathstat=None, a=None, sigma=None, s0sq=None, T=None,
                    uref=None, kappa: int = 0, err=None, stream=None):
     """mg_error_vs_exact: per-path relative Frobenius error on the kappa window."""
@@ -408,6 +463,22 @@ def error_vs_exact(ops_or_grid, u, pathstat=None, a=None, sigma=None, s0sq=None,
         ctypes.byref(grid), ctypes.byref(ex) if ex is not None else None, _ptr(pathstat), _ptr(u),
         _ptr(uref), P, kappa, _ptr(err), _stream(stream)))
     return err
+
+
+@_stream_scoped
+def check_flags(flags, stream=None):
+    """mg_check_flags: waits for the stream; returns (OR of all flags, first
+    flagged path or -1).  Raises MagnusError(MG_ENONFINITE) if any path is
+    flagged."""
+    import torch
+    if not (isinstance(flags, torch.Tensor) and flags.is_cuda and flags.dtype == torch.int32
+            and flags.is_contiguous()):
+        raise TypeError("flags must be a contiguous int32 CUDA tensor")
+    bits = ctypes.c_int32(0)
+    first = ctypes.c_int64(-1)
+    _check(load_library().mg_check_flags(_ptr(flags), flags.numel(), ctypes.byref(bits),
+                                         ctypes.byref(first), _stream(stream)))
+    return int(bits.value), int(first.value)
 
 
 def timing_enable(on: bool = True):

@@ -708,6 +708,42 @@ mg_status mg_error_vs_exact(const mg_grid* grid, const mg_exact* ex, const doubl
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_error_vs_exact");
 }
 
+mg_status mg_check_flags(const int32_t* flags, int64_t P, int32_t* bits_out, int64_t* first_out,
+                         void* stream) {
+    g_last_error.clear();
+    if (bits_out) *bits_out = 0;
+    if (first_out) *first_out = -1;
+    if (P < 0) return mg_fail(MG_ESHAPE, "mg_check_flags: P < 0");
+    if (P == 0) return MG_OK;
+    if (!flags) return mg_fail(MG_EINVAL, "mg_check_flags: NULL flags");
+    std::vector<int32_t> h;
+    try {
+        h.resize((size_t)P);
+    } catch (const std::bad_alloc&) {
+        return mg_fail(MG_ENOMEM, "mg_check_flags: out of host memory");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(h.data(), flags, (size_t)P * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "mg_check_flags");
+    int32_t bits = 0;
+    int64_t first = -1, count = 0;
+    for (int64_t p = 0; p < P; ++p)
+        if (h[(size_t)p]) {
+            bits |= h[(size_t)p];
+            if (first < 0) first = p;
+            ++count;
+        }
+    if (bits_out) *bits_out = bits;
+    if (first_out) *first_out = first;
+    if (count == 0) return MG_OK;
+    return mg_fail(MG_ENONFINITE, "mg_check_flags: " + std::to_string(count) + " of " +
+                                      std::to_string(P) + " paths flagged (first: path " +
+                                      std::to_string(first) + ", bits " + std::to_string(bits) +
+                                      ")");
+}
+
 mg_status mg_timing_enable(int32_t on) {
     std::lock_guard<std::mutex> lk(g_timing_mu);
     g_timing_on = on != 0;
