@@ -644,6 +644,7 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, F32C, 0); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, F32C, 0); \
     if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, F32C, 0); \
+    if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX, F32C, 0); \
     return hipErrorInvalidValue;
 #define MG_COOP_SHAPES_ND(PX, RJ, NW, FULLX, F32C, CALL)                                       \
     if (ops->ND == 3) {                                                                        \
