@@ -192,6 +192,31 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
                           void* stream);
 
 /* --------------------------------------------------------------------------
+ * mg_magnus_expmv_noalloc  (for callers that cannot allocate device memory:
+ *                           code under HIP graph capture, tight serving
+ *                           loops, harnesses that forbid hipMalloc)
+ *
+ * mg_magnus_expmv without a workspace argument: the same kernels, with the
+ * workspace (per-(path, step) tables and the cooperative exchange area) in a
+ * fixed device array of MG_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends.  The call allocates no
+ * device or host memory and creates no events (the timing instrumentation
+ * does not see it).  Arguments, results and errors as for mg_magnus_expmv;
+ * the caller still provides u0, uT, stats and flags.
+ *   A call whose mg_workspace_bytes(ops, P, K, precision) exceeds
+ *   MG_NOALLOC_SCRATCH_BYTES returns MG_ENOMEM before anything is enqueued.
+ *   Every call on one device shares that device's array, and each call
+ *   writes all of the array it reads: calls that may overlap on one device
+ *   (different streams without ordering between them) race and must not be
+ *   issued; calls on one stream are ordered and safe.
+ * ------------------------------------------------------------------------ */
+#define MG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mg_status mg_magnus_expmv_noalloc(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
+                                  const double* u0, int32_t u0_broadcast, double* uT,
+                                  int32_t precision, double tol, int32_t* stats, int32_t* flags,
+                                  void* stream);
+
+/* --------------------------------------------------------------------------
  * mg_autotune_expmv  (kernel shape of the Taylor chain of mg_magnus_expmv)
  *
  * Times the workgroup shapes the library holds for this grid (x points per

@@ -26,7 +26,8 @@ MG_FP64, MG_FP32C = 0, 1
 PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
-           "mg_workspace_bytes", "mg_magnus_expmv", "mg_workspace_bytes_multi",
+           "mg_workspace_bytes", "mg_magnus_expmv", "mg_magnus_expmv_noalloc",
+           "mg_workspace_bytes_multi",
            "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_select_magnus_steps",
            "mg_select_magnus_steps_per_path", "mg_iterated_integrals_steps",
            "mg_euler_increments",
@@ -85,6 +86,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_euler_workspace_bytes.argtypes = [vp, i64]
     lib.mg_euler_workspace_bytes.restype = sz
     lib.mg_magnus_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, vp, vp, vp]
+    lib.mg_magnus_expmv_noalloc.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, vp, vp]
     lib.mg_select_magnus_steps.argtypes = [vp, vp, vp, i64, i64, dbl, vp, i32, i32, i32, dbl, i32,
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_double),
@@ -108,7 +110,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_timing_enable.argtypes = [i32]
     lib.mg_timing_read.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for name in ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
-                 "mg_magnus_expmv", "mg_magnus_expmv_multi", "mg_euler_increments",
+                 "mg_magnus_expmv", "mg_magnus_expmv_noalloc", "mg_magnus_expmv_multi",
+                 "mg_euler_increments",
                  "mg_euler_step", "mg_error_vs_exact", "mg_check_flags", "mg_timing_enable",
                  "mg_timing_read", "mg_timing_reset"):
         getattr(lib, name).restype = i32
@@ -291,6 +294,29 @@ def magnus_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float =
     _check(load_library().mg_magnus_expmv(
         ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
         float(tol), _ptr(ws), ws.numel(), _ptr(stats), _ptr(flags), _stream(stream)))
+    return uT, flags, stats
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # MG_NOALLOC_SCRATCH_BYTES
+
+
+@_stream_scoped
+def magnus_expmv_noalloc(ops: Operators, coef, u0, uT, flags=None, stats=None,
+                         precision: str = "fp64", tol: float = 0.0, stream=None):
+    """mg_magnus_expmv_noalloc: mg_magnus_expmv with the library's fixed
+    scratch array as workspace.  The caller passes every output (uT [P][N],
+    optional flags [P] int32 and stats [P][K][2] int32); nothing is allocated."""
+    _dev_f64(coef, "coef")
+    _dev_f64(u0, "u0")
+    _dev_f64(uT, "uT")
+    P, K, six = coef.shape
+    N = ops.grid.nx * ops.grid.nv
+    bcast = 1 if u0.dim() == 1 else 0
+    if u0.numel() != (N if bcast else P * N) or uT.numel() != P * N:
+        raise ValueError("u0 or uT has the wrong size")
+    _check(load_library().mg_magnus_expmv_noalloc(
+        ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
+        float(tol), _ptr(stats), _ptr(flags), _stream(stream)))
     return uT, flags, stats
 
 

@@ -33,9 +33,10 @@ struct TimingScope {
     hipStream_t s;
     const char* name;
     bool on;
+    // n == nullptr: never timed (no events are created)
     TimingScope(const char* n, hipStream_t st) : s(st), name(n) {
         std::lock_guard<std::mutex> lk(g_timing_mu);
-        on = g_timing_on;
+        on = g_timing_on && n != nullptr;
         if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, s);
         else
@@ -249,13 +250,15 @@ mg_status expmv_prepare(ExpmvCall& c, const std::string& where) {
     return MG_OK;
 }
 
-// Launches a prepared call with its workspace.
-mg_status expmv_launch(const ExpmvCall& c, char* ws, hipStream_t s, const std::string& where) {
+// Launches a prepared call with its workspace.  `timed`: bracket the Taylor
+// kernel with the timing instrumentation when it is on (creates HIP events).
+mg_status expmv_launch(const ExpmvCall& c, char* ws, hipStream_t s, const std::string& where,
+                       bool timed = true) {
     if (c.P == 0) return MG_OK;
     char* tables = ws;
     hipError_t e = launch_assemble(c.ops, c.coef, c.P, c.K, c.tol, c.precision, tables, s);
     if (e != hipSuccess) return hip_fail(e, (where + " (assemble)").c_str());
-    TimingScope ts("expmv", s);
+    TimingScope ts(timed ? "expmv" : nullptr, s);
     if (c.fam == Family::Resident)
         e = launch_expmv_resident(c.ops, tables, c.tbytes, c.P, c.K, c.u0, c.bcast, c.uT, c.tol,
                                   c.precision, c.stats, c.flags, s, false);
@@ -292,6 +295,62 @@ mg_status mg_magnus_expmv(const mg_ops* ops, const double* coef, int64_t P, int3
     if (ws_bytes < c.need)
         return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
     return expmv_launch(c, (char*)ws, (hipStream_t)stream, where);
+}
+
+namespace {
+// Scratch memory of mg_magnus_expmv_noalloc: its workspace (the per-(path,
+// step) tables and the cooperative exchange area) in a device array that the
+// runtime places on every device the library runs on when the code object
+// is loaded there, held until the process ends.  Host code never names the
+// array in device work: on the host `scratch` is only a stand-in; its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = MG_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (looked up on
+// the first call on that device, with that device current).
+mg_status scratch_on_current_device(char** out, const std::string& where) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, (where + " (hipGetDevice)").c_str());
+    if (dev < 0 || dev >= kMaxDevices)
+        return mg_fail(MG_EUNSUPPORTED, where + ": device index beyond " + std::to_string(kMaxDevices));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, (where + " (hipGetSymbolAddress)").c_str());
+        if (!ptr) return mg_fail(MG_EHIP, where + ": no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return MG_OK;
+}
+}  // namespace
+
+mg_status mg_magnus_expmv_noalloc(const mg_ops* ops, const double* coef, int64_t P, int32_t K,
+                                  const double* u0, int32_t u0_broadcast, double* uT,
+                                  int32_t precision, double tol, int32_t* stats, int32_t* flags,
+                                  void* stream) {
+    g_last_error.clear();
+    ExpmvCall c{ops, coef, P, K, u0, u0_broadcast, uT, precision, tol, stats, flags};
+    const std::string where = "mg_magnus_expmv_noalloc";
+    mg_status st = expmv_prepare(c, where);
+    if (st != MG_OK || P == 0) return st;
+    if (c.need > kScratchBytes)
+        return mg_fail(MG_ENOMEM, where + ": the call needs " + std::to_string(c.need) +
+                                      " bytes of scratch memory, above the fixed " +
+                                      std::to_string(kScratchBytes) +
+                                      " (use mg_magnus_expmv with a workspace)");
+    char* ws = nullptr;
+    if ((st = scratch_on_current_device(&ws, where)) != MG_OK) return st;
+    // same kernels as mg_magnus_expmv; the timing instrumentation (which
+    // creates HIP events) stays off here
+    return expmv_launch(c, ws, (hipStream_t)stream, where, false);
 }
 
 namespace {

@@ -57,6 +57,8 @@ def test_shape_checks_before_any_device_call(lib):
     # NULL ops
     assert lib.mg_magnus_expmv(None, None, 1, 1, None, 1, None, 0, 0.0, None, 0, None, None,
                                None) == mg.MG_EINVAL
+    assert lib.mg_magnus_expmv_noalloc(None, None, 1, 1, None, 1, None, 0, 0.0, None, None,
+                                       None) == mg.MG_EINVAL
     assert lib.mg_euler_step(None, None, 1, None, 1, 0.1, 0, None, 0, None, None) == mg.MG_EINVAL
     assert lib.mg_workspace_bytes(None, 4, 4, 0) == 0
 
