@@ -8,10 +8,12 @@ The Euler-Maruyama baseline is timed the same way at the smallest power-of-two
 step count whose mean error matches the Magnus error (within 2 %), and the
 CPU oracle is timed on a bounded sample of paths on the host cores.
 
-Workload (default): 128x128 grid on [-6,6]^2, constant-coefficient stochastic
+Workload (default): 256x256 grid on [-5,5]^2, constant-coefficient stochastic
 Langevin SPDE (f^x = -v, g^vv = 1, sigma^v = 0.5), Gaussian initial density
-N(0, 0.25 I), T = 1, 1024 paths with 2^14 fine increments, Magnus order 2 with
-16 steps, FP64.  Inputs are synthetic and resident in HBM before timing.
+N(0, 0.25 I), T = 1, 4096 paths with 2^14 fine increments, Magnus order 3 with
+32 steps; the figure of record is the FP64 path, the compensated FP32 form is
+run on the same batch beside it.  Inputs are synthetic and resident in HBM
+before timing.
 
 Prints ONE JSON line.
 """
@@ -52,18 +54,36 @@ TRAFFIC = {
 }
 
 
-def _kernel_source_hash():
+def _kernel_source_hash(kernel_file="expmv_resident.hip"):
     import hashlib
     h = hashlib.sha256()
-    for f in ("expmv_resident.hip", "kernel_common.h"):
+    for f in (kernel_file, "kernel_common.h"):
         with open(os.path.join(ROOT, "paper_2207_09776_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(workload):
-    rec = TRAFFIC.get((_kernel_source_hash(), workload))
+def traffic_for(workload, kernel_file="expmv_resident.hip"):
+    rec = TRAFFIC.get((_kernel_source_hash(kernel_file), workload))
     return None if rec is None else rec[0] + rec[1]
+
+
+def host_cpu():
+    """CPU model and the host's logical CPUs (for the CPU baseline record)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
 def log(msg):
@@ -138,13 +158,13 @@ def _oracle_worker(args):
 
 
 def cpu_baseline(name: str):
+    """The oracle on one or two paths per host process, one process per usable
+    host CPU (at most 16: the CPU share of one GPU on the measurement host)."""
     import multiprocessing as mpr
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
-    per = 2
+    import workloads as wl
+    host = host_cpu()
+    cores = max(1, min(host["usable_cpus"], 16))
+    per = 2 if wl.WORKLOADS[name].n <= 128 else 1
     jobs = [(name, i * per, per) for i in range(cores)]
     ctx = mpr.get_context("spawn")
     t0 = time.perf_counter()
@@ -158,6 +178,7 @@ def cpu_baseline(name: str):
             "sample": f"{npaths} paths of the benchmark workload (paths 0..{npaths - 1}), "
                       f"{per} per process, {what}, wall {wall:.1f} s "
                       f"including operator build",
+            **host,
             "cpu_seconds": float(sum(r[0] for r in res)),
             "mean_err": (float(np.mean([e for r in res for e in r[1]]))
                          if any(r[1] for r in res) else None)}
@@ -356,7 +377,11 @@ def run_mixed(args, w):
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    torch.cuda.synchronize()
+    mg.timing_reset()
+    for g in groups:
+        g["ops"].close()
 
 
 def paper_sweep(args):
@@ -435,7 +460,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="const-128-p1024-m2-k16")
+    ap.add_argument("--workload", default="const-256-p4096-m3-k32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-euler", action="store_true", help="skip the Euler baseline")
     ap.add_argument("--no-fp32c", action="store_true", help="skip the compensated FP32 run")
@@ -584,6 +609,7 @@ def main():
 
     m64 = measure("fp64", args.steps, args.warmup)
     g64 = measure_graph("fp64", args.steps)
+    u64 = uT.clone() if not args.no_fp32c else None      # for the FP32C distance
     eager_ms = m64["ms_per_step"]
     # the figure of record: graph replays where the step is captured (they
     # must reproduce the eager result), else the eager steps
@@ -604,9 +630,10 @@ def main():
     flops = float(terms) * N * flops_pt
     k_avg_s = m64["launch_ms"] / 1e3
     achieved = flops / k_avg_s
+    kfile = "expmv_resident.hip" if w.n <= 128 else "expmv_coop.hip"
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK,
-                "traffic": traffic_for(w.name),
+                "traffic": traffic_for(w.name, kfile),
                 "kernel": "expmv_resident_kernel" if w.n <= 128 else "expmv_coop_kernel",
                 "flops_per_point_term": flops_pt, "taylor_terms": terms,
                 "terms_per_path": terms / P, "substeps_per_path": m64["substeps"] / P,
@@ -627,11 +654,14 @@ def main():
         f"{upload['ms']:.3f} ms ({upload['GBps']:.1f} GB/s); with it "
         f"{upload['paths_per_s_with_upload']:.0f} paths/s")
 
-    # compensated FP32 at the same K: errors must agree within 1 % of the FP64 error
+    # compensated FP32 at the same K: errors must agree within 1 % of the FP64
+    # error; the distance of its solutions from the FP64 ones is reported too
     fp32c = None
     if not args.no_fp32c:
         m32 = measure("fp32c", max(1, args.steps // 2), 1)
         rel = abs(m32["mean_err"] - mean_err) / mean_err
+        dist = ((uT - u64).norm(dim=1) / u64.norm(dim=1)).cpu().numpy()
+        del u64
         fl32 = float(m32["terms"]) * N * flops_pt
         fp32c = {"paths_per_s": P / (m32["ms_per_step"] / 1e3), "ms_per_step": m32["ms_per_step"],
                  "launch_ms": m32["launch_ms"], "mean_err": m32["mean_err"],
@@ -639,9 +669,14 @@ def main():
                  "flagged_paths": m32["flagged"], "terms_per_path": m32["terms"] / P,
                  "substeps_per_path": m32["substeps"] / P,
                  "achieved_TFLOPs": fl32 / (m32["launch_ms"] / 1e3) / 1e12,
-                 "speedup_vs_fp64": eager_ms / m32["ms_per_step"]}
+                 "frac_of_fp32_peak": fl32 / (m32["launch_ms"] / 1e3) / FP32_VECTOR_PEAK,
+                 "speedup_vs_fp64": eager_ms / m32["ms_per_step"],
+                 "dist_to_fp64": {"what": "||u32 - u64|| / ||u64|| per path (Frobenius, full grid)",
+                                  "max": float(dist.max()), "mean": float(dist.mean()),
+                                  "paths_above_1e-5": int((dist > 1e-5).sum())}}
         log(f"FP32C: {fp32c['paths_per_s']:.1f} paths/s, Err {m32['mean_err']:.4e} "
-            f"(rel. diff {rel:.2e}), {fp32c['terms_per_path']:.0f} terms/path")
+            f"(rel. diff {rel:.2e}), {fp32c['terms_per_path']:.0f} terms/path, "
+            f"distance to FP64 max {dist.max():.2e} mean {dist.mean():.2e}")
 
     # Euler-Maruyama at matched error
     euler = None
@@ -782,7 +817,13 @@ def main():
         "fp32c": fp32c,
         "cpu_baseline": cpu,
     }
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    # explicit teardown before the interpreter exits: the library's tables and
+    # timing events are released while the HIP runtime is still up
+    torch.cuda.synchronize()
+    mg.timing_reset()
+    for o in {id(x): x for x in (ops, locals().get("o2"), locals().get("o3")) if x is not None}.values():
+        o.close()
 
 
 if __name__ == "__main__":

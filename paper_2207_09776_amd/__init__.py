@@ -66,6 +66,9 @@ class mg_exact(ctypes.Structure):
 
 
 _lib = None
+# bound at import: module globals (sys included) may already be None while
+# objects are collected at interpreter exit
+_is_finalizing = sys.is_finalizing
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -218,7 +221,7 @@ class Operators:
         # No HIP call while the interpreter shuts down: the HIP runtime and the
         # profiler's interception may already be gone then; the process exit
         # releases the device memory.
-        if sys.is_finalizing():
+        if _is_finalizing is None or _is_finalizing():
             return
         try:
             self.close()

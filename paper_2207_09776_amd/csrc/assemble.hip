@@ -8,7 +8,8 @@
 // ||Y - mu I||_1 / s <= theta_m (truncated-Taylor thresholds of Al-Mohy and
 // Higham for the requested tolerance).  The table written for (p, k) holds the
 // header (s, m, exp(mu/s), mu, norm, flag) and the rows of (Y - mu I)/s, in
-// FP64, or rounded once to FP32 for the compensated FP32 form.
+// FP64, or rounded to FP32 for the compensated FP32 form (with the rounding
+// residual of every band moved into its centre entry, see below).
 //
 // Column sums.  With M = sum_q V_q (x) Dt^q (Dt = tridiag(-1,0,1)), column
 // (i', j') of Y - mu I has entries in rows (i, j), |j - j'| <= R, i - i' in
@@ -160,17 +161,48 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
     __syncthreads();
     const double inv_s = 1.0 / hdr[0];
     char* rows = a.tables + pk * a.tbytes + 64;
-    for (int idx = t; idx < a.nv_pad * a.NBP; idx += kThreads) {
-        const int j = idx / a.NBP, e = idx % a.NBP;
-        double v = 0.0;
-        if (j < nv) {
-            v = coeff(a, c, j, e);
-            if (e == o0 + a.R0) v -= mu;
-        }
-        if (a.f32)
-            reinterpret_cast<float*>(rows)[idx] = (float)(v * inv_s);
-        else
+    if (!a.f32) {
+        for (int idx = t; idx < a.nv_pad * a.NBP; idx += kThreads) {
+            const int j = idx / a.NBP, e = idx % a.NBP;
+            double v = 0.0;
+            if (j < nv) {
+                v = coeff(a, c, j, e);
+                if (e == o0 + a.R0) v -= mu;
+            }
             reinterpret_cast<double*>(rows)[idx] = v * inv_s;
+        }
+        return;
+    }
+    // FP32 rows.  Rounding every entry on its own would change the sum of each
+    // band by up to 2^-24 times the sum of its magnitudes; on smooth data the
+    // operator acts through these sums (the large entries of a second
+    // difference cancel), so that change becomes a spurious growth rate of
+    // the order of 2^-24 ||Y||, the same in every sub-step of a Magnus step.
+    // Each band's centre entry therefore takes up the rounding residual of
+    // the others: the FP32 band sums equal the FP64 ones to one rounding of
+    // the (small, trace-shifted) centre.
+    for (int j = t; j < a.nv_pad; j += kThreads) {
+        float* row = reinterpret_cast<float*>(rows) + (size_t)j * a.NBP;
+        if (j >= nv) {
+            for (int e = 0; e < a.NBP; ++e) row[e] = 0.0f;
+            continue;
+        }
+        auto band = [&](int off, int rad, double shift) {
+            double resid = 0.0;
+            for (int b = -rad; b <= rad; ++b) {
+                if (b == 0) continue;
+                const double v = coeff(a, c, j, off + b + rad) * inv_s;
+                const float f = (float)v;
+                row[off + b + rad] = f;
+                resid += v - (double)f;
+            }
+            row[off + rad] = (float)((coeff(a, c, j, off + rad) - shift) * inv_s + resid);
+        };
+        band(o0, a.R0, mu);
+        band(o1, a.R1, 0.0);
+        if (v2) band(o2, a.R2, 0.0);
+        for (int f = 0; f < a.ND; ++f) band(o3 + f * wl, a.RW, 0.0);
+        for (int e = o3 + a.ND * wl; e < a.NBP; ++e) row[e] = 0.0f;
     }
 }
 

@@ -92,19 +92,26 @@ __device__ inline T waves_max(T x) {
     return lane_value<NW - 1>(x);
 }
 
-// 1/j! (FP64 chain) and 1/j (FP32 chain) for j <= 63, formed by the same
-// sequence of correctly rounded operations the chain would use at run time.
+// 1/j! (FP64 chain) for j <= 63, formed by the same sequence of correctly
+// rounded operations the chain would use at run time, and 1/j for the FP32
+// chain as a float plus its residual: c_j = y (1/j) is formed as
+// fma(y, inv_j, y * inv_j_lo), so the scaling carries no systematic bias (a
+// single rounded 1/j would scale every term j of every sub-step by the same
+// factor 1 + O(2^-24), which adds up over the sub-steps of a path).
 struct FactorTables {
     double inv_fact[64];
     float inv_j[64];
+    float inv_j_lo[64];
 };
 constexpr FactorTables make_factor_tables() {
     FactorTables t{};
     t.inv_fact[0] = 1.0;
     t.inv_j[0] = 1.0f;
+    t.inv_j_lo[0] = 0.0f;
     for (int j = 1; j < 64; ++j) {
         t.inv_fact[j] = t.inv_fact[j - 1] / (double)j;
         t.inv_j[j] = (float)(1.0 / (double)j);
+        t.inv_j_lo[j] = (float)(1.0 / (double)j - (double)t.inv_j[j]);
     }
     return t;
 }
@@ -397,13 +404,13 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
                     else
                         return [rows](int r, int e) -> T { return rows[r * NBP + e]; };
                 }();
-                const T invj = kFactors.inv_j[j];
+                const T invj = kFactors.inv_j[j], invj_lo = kFactors.inv_j_lo[j];
                 T mc = 0, mf = 0;
                 // c_j = Y' c_{j-1} / j goes to `out`; F = hi + lo gains c_j (Kahan)
                 auto kahan = [&](int r, T (&y)[PX]) {
 #pragma unroll
                     for (int q = 0; q < PX; ++q) {
-                        const T x = y[q] * invj;
+                        const T x = fma(y[q], invj, y[q] * invj_lo);
                         y[q] = x;
                         const T a = x + lo[r][q];
                         const T t = hi[r][q] + a;

@@ -56,7 +56,8 @@ struct mg_ops {
 //   64-byte header: [int32 s, pad] [int32 m, pad] [f64 exp(mu/s)] [f64 mu]
 //                   [f64 ||Y - mu I||_1] [int32 flag, pad] [2 x f64 reserved]
 //   then nv_pad rows of NBP coefficients of (Y - mu I)/s, FP64 (MG_FP64) or
-//   FP32 rounded once from FP64 (MG_FP32C); records are 64-byte aligned.
+//   FP32 rounded from FP64 with each band's rounding residual in its centre
+//   entry (MG_FP32C); records are 64-byte aligned.
 inline size_t mg_table_bytes(const mg_ops* ops, int precision) {
     const size_t elem = precision == MG_FP32C ? 4 : 8;
     size_t b = 64 + (size_t)ops->nv_pad * ops->NBP * elem;
@@ -98,6 +99,9 @@ int resident_candidates(int nx, int nv, int (*shapes)[3], int max);
 // the most rows per workgroup any cooperative kernel shape for this nx uses
 // (operator tables are padded to a multiple of it; 0: no shape)
 int coop_rows_max(int nx);
+// table rows the cooperative kernels for this grid need: nv rounded up to
+// the rows of a workgroup (0: no kernel)
+int coop_table_rows(int nx, int nv);
 // cooperative kernels: the Taylor chain and Euler-Maruyama (FP64)
 enum class CoopKind { Expmv, Euler };
 // a cooperative kernel of this kind exists for this operator and precision

@@ -426,10 +426,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     }
     // table rows are padded to the rows the kernel shape covers
     int rows = resident_rows(nx, nv);
-    if (rows == 0) {
-        const int rw = coop_rows_max(nx);
-        if (rw > 0) rows = (nv + rw - 1) / rw * rw;
-    }
+    if (rows == 0) rows = coop_table_rows(nx, nv);
     ops->nv_pad = std::max(nv, rows);
     ops->basis_host.assign((size_t)MG_NBASIS * ops->nv_pad * ops->NBP, 0.0);
     const double fold[3] = {1.0, 1.0 / (2.0 * dx), 1.0 / (4.0 * dx * dx)};

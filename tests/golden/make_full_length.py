@@ -30,8 +30,8 @@ OUT = os.path.join(HERE, "full")
 
 # name -> (workload, group index in a mixed workload or None, path index)
 RECORDS = {
-    "const-256-p4096-m3-k32_p0": ("const-256-p4096-m3-k32-fp32c", None, 0),
-    "const-256-p4096-m3-k32_p4095": ("const-256-p4096-m3-k32-fp32c", None, 4095),
+    "const-256-p4096-m3-k32_p0": ("const-256-p4096-m3-k32", None, 0),
+    "const-256-p4096-m3-k32_p4095": ("const-256-p4096-m3-k32", None, 4095),
     "var-512-p512-m2-k256_p0": ("var-512-p512-m2-k256", None, 0),
     "var-512-p512-m2-k256_p511": ("var-512-p512-m2-k256", None, 511),
     "mixed-1024-p64-m2-k512_p0": ("mixed-64-256-1024-m2-fp32c", 2, 0),

@@ -337,7 +337,7 @@ def test_full_size_256_fp32c_sampled_path():
     """The 256x256 workload (4096 paths, m3, 32 steps, compensated FP32) in
     the configuration the benchmark would run; path 1234 is checked against
     the FP64 oracle (1e-5)."""
-    w = wl.WORKLOADS["const-256-p4096-m3-k32-fp32c"]
+    w = wl.WORKLOADS["const-256-p4096-m3-k32"]
     say(f"magnus full {w.name}")
     g, B, A, basis, ops = setup_problem(w.n, w.n, w.lo, w.hi, w.coefficients(), w.order)
     dW = wl.brownian_increments(w.seed, w.paths, w.Nf)

@@ -122,11 +122,12 @@ WORKLOADS: Dict[str, Workload] = {
                                    euler_steps=2 ** 12),
     "const-128-p1024-m2-k16": Workload("const-128-p1024-m2-k16", 128, -6.0, 6.0, 1024, 16, 2,
                                         2 ** 14, 2, euler_steps=2 ** 14),
-    # the Euler baseline of this workload is timed on 64 paths (one per group
-    # of workgroups the GPU holds at once) and scaled to paths/s
-    "const-256-p4096-m3-k32-fp32c": Workload("const-256-p4096-m3-k32-fp32c", 256, -5.0, 5.0, 4096,
-                                              32, 3, 2 ** 14, 3, precision="fp32c",
-                                              euler_time_paths=64),
+    # The largest single-GPU constant-coefficient batch (the cooperative
+    # kernel: several workgroups per path), run in FP64 and in the FP32 form.
+    # The Euler baseline of this workload is timed on 64 paths (one per group
+    # of workgroups the GPU holds at once) and scaled to paths/s.
+    "const-256-p4096-m3-k32": Workload("const-256-p4096-m3-k32", 256, -5.0, 5.0, 4096,
+                                        32, 3, 2 ** 14, 3, euler_time_paths=64),
     # The variable-coefficient workload at 512^2.  K = 256: the order-2
     # logarithm (its c3 [B,A] term) has an unbounded exponential at K = 64 on
     # this grid, as in the constant case, and at K = 128 two of the first 16
