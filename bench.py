@@ -51,6 +51,9 @@ TRAFFIC = {
     # (source hash, workload): (bytes read, bytes written) per launch;
     # profiles/expmv_resident_counters_const-128-p1024-m2-k16.txt
     ("68df813b853601cf", "const-128-p1024-m2-k16"): (133691 * 1024 * 2.000, 131110 * 1024 * 1.000),
+    # profiles/expmv_coop_counters_const-256-p4096-m3-k32.txt (FP64 in-place kernel)
+    ("7434bc1724b4b8b2", "const-256-p4096-m3-k32"): (216200462 * 1024 * 2.000,
+                                                     1697692000 * 1024 * 1.000),
 }
 
 
