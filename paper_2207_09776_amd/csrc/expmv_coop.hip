@@ -43,7 +43,9 @@ constexpr int kSpinLimit = 1 << 22;
 // Exchange area of a cooperative launch (in the caller's workspace, zeroed
 // before the launch) and the group layout.
 struct XArea {
-    char* xh;          // halo rows   [ngroups][G][2 parity][2 side][RHX][nx] of T
+    char* xh;          // halo rows   [ngroups][G][2 parity][2 side][RHX][64*PX] of T
+                       // (point q of lane l at q*64 + l: each store or load
+                       // instruction of a wave covers 64 consecutive values)
     double* xn;        // norms       [ngroups][G][2 parity][NW waves][2]
     int* fl;           // counters    [ngroups][G]
     int* abort_word;
@@ -157,17 +159,17 @@ struct CoopGroup {
         }
         // this group's slices of the exchange area (offsets within them fit
         // 32 bits: G <= 64 members)
-        xh_g = reinterpret_cast<T*>(x.xh) + (size_t)grp * x.G * 2 * 2 * kRHX * nx;
+        xh_g = reinterpret_cast<T*>(x.xh) + (size_t)grp * x.G * 2 * 2 * kRHX * (64 * PX);
         xn_g = x.xn + (size_t)grp * x.G * 2 * NW * 2;
     }
     T* xh_g;
     double* xn_g;
     __device__ __forceinline__ T* xh_row(int member, int par, int side, int s) const {
-        return xh_g + (size_t)(unsigned)((((member * 2 + par) * 2 + side) * kRHX + s) * nx);
+        return xh_g + (size_t)(unsigned)((((member * 2 + par) * 2 + side) * kRHX + s) * (64 * PX));
     }
-    // this lane's first point in that row (its PX points follow)
+    // this lane's first point in that row (its point q is q*64 further)
     __device__ __forceinline__ T* xh_lane(int member, int par, int side, int s) const {
-        return xh_row(member, par, side, s) + (unsigned)(lane * PX);
+        return xh_row(member, par, side, s) + (unsigned)lane;
     }
     // per member and parity: NW pairs (one per wave) of norms
     __device__ __forceinline__ double* xn_at(int member, int par, int wave) const {
@@ -182,7 +184,7 @@ struct CoopGroup {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
-                    if (i < nx) xstore(xh_lane(g, par, 0, s) + q, d[s][q]);
+                    if (i < nx) xstore(xh_lane(g, par, 0, s) + q * 64, d[s][q]);
                 }
         }
         if (w == NW - 1 && g + 1 < x.G) {
@@ -191,7 +193,7 @@ struct CoopGroup {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
-                    if (i < nx) xstore(xh_lane(g, par, 1, s) + q, d[RJ - RH + s][q]);
+                    if (i < nx) xstore(xh_lane(g, par, 1, s) + q * 64, d[RJ - RH + s][q]);
                 }
         }
     }
@@ -242,7 +244,7 @@ struct CoopGroup {
                 for (int q = 0; q < PX; ++q) {
                     const int i = lane * PX + q;
                     T v = T(0);
-                    if (g > 0 && i < nx) v = xload(xh_lane(g - 1, par, 1, s) + q);
+                    if (g > 0 && i < nx) v = xload(xh_lane(g - 1, par, 1, s) + q * 64);
                     top[s][q] = v;
                 }
         }
@@ -253,7 +255,7 @@ struct CoopGroup {
             for (int q = 0; q < PX; ++q) {
                 const int i = lane * PX + q;
                 T v = T(0);
-                if (last && g + 1 < x.G && i < nx) v = xload(xh_lane(g + 1, par, 0, s) + q);
+                if (last && g + 1 < x.G && i < nx) v = xload(xh_lane(g + 1, par, 0, s) + q * 64);
                 bot[s][q] = last ? v : bot[s][q];
             }
     }
@@ -1075,7 +1077,9 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     plan->xcd_map = xcd_map;
     plan->lds = lds;
     plan->threads = 64 * nw;
-    plan->xh_bytes = ((size_t)ngroups * G * 2 * 2 * kRHX * ops->grid.nx * elem + 255) & ~(size_t)255;
+    CoopShape sh;
+    pick_coop_shape(ops->grid.nx, sh);
+    plan->xh_bytes = ((size_t)ngroups * G * 2 * 2 * kRHX * (64 * sh.PX) * elem + 255) & ~(size_t)255;
     plan->xn_bytes = ((size_t)ngroups * G * 2 * nw * 2 * sizeof(double) + 255) & ~(size_t)255;
     plan->fl_bytes = ((size_t)ngroups * G * sizeof(int) + 256 + 255) & ~(size_t)255;
     plan->bytes = plan->xh_bytes + plan->xn_bytes + plan->fl_bytes;
