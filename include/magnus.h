@@ -55,6 +55,16 @@ typedef int32_t mg_status;
 #define MG_FLAG_NORM      2    /* ||Y_{p,k} - mu I||_1 exceeded the supported range */
 #define MG_FLAG_ABORT     4    /* a multi-workgroup launch gave up waiting for a
                                   workgroup of its group (result not valid)    */
+#define MG_FLAG_NEGATIVE  8    /* mg_magnus_expmv: the initial state was non-negative
+                                  and the final one has a negative part beyond 0.1
+                                  of its maximum.  The exact solution of the forward
+                                  equation stays a density, so this marks a Magnus
+                                  step beyond the convergence region of the
+                                  expansion (Theorem 'convergence'): rerun the path
+                                  with more steps (the result is still written).
+                                  A gross-failure check: the central differences
+                                  leave small negative values on coarse grids
+                                  (a few 1e-2 of the maximum), which stay unflagged. */
 
 /* Precision forms of the Taylor chain (the state u is FP64 in both). */
 #define MG_FP64  0             /* every operation in FP64                     */

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libmagnus.so")
 
 MG_OK, MG_EINVAL, MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP, MG_ENOMEM = 0, -1, -2, -3, -4, -5
 MG_ENONFINITE = -6
-MG_FLAG_NONFINITE, MG_FLAG_NORM, MG_FLAG_ABORT = 1, 2, 4
+MG_FLAG_NONFINITE, MG_FLAG_NORM, MG_FLAG_ABORT, MG_FLAG_NEGATIVE = 1, 2, 4, 8
 MG_FP64, MG_FP32C = 0, 1
 PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 

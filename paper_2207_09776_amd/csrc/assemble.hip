@@ -20,7 +20,9 @@
 // (x-dependent coefficients) add w_t a_t(i') to the entry in row i'; there the
 // sum uses |c + sum_t w_t m_t| + sum_t |w_t| h_t with m_t, h_t the midpoint and
 // half-width of the values of a_t, an upper bound of the exact column sum, so
-// (m, s) stay admissible (at worst s is larger than needed).
+// (m, s) stay admissible (at worst s is larger than needed).  Chain terms
+// C (x) diag(alpha) Dt diag(beta) add at most |C| max|alpha| max|beta| per x
+// neighbour of the column.
 
 #include <cmath>
 
@@ -44,11 +46,19 @@ struct AsmArgs {
     int ND, RW;                // x-dependent factors (0: none) and their band radius
     const double* xstat;       // per factor {sum, midpoint, half-width, 0}
     int use24;                 // theta table for 2^-24 instead of 2^-53
+    int NC, NCB;               // chain terms and their coefficients per row (FP64 only)
+    const double* basis_c;     // chain section of the basis [6][nv_pad][NCB]
+    const double* cstat;       // per chain {max|alpha| max|beta|, 0, 0, 0}
 };
 
 __device__ inline double coeff(const AsmArgs& a, const double* c, int j, int idx) {
     double v = 0.0;
     for (int l = 0; l < a.nact; ++l) v += c[l] * a.basis[((size_t)l * a.nv_pad + j) * a.NBP + idx];
+    return v;
+}
+__device__ inline double coeff_c(const AsmArgs& a, const double* c, int j, int idx) {
+    double v = 0.0;
+    for (int l = 0; l < a.nact; ++l) v += c[l] * a.basis_c[((size_t)l * a.nv_pad + j) * a.NCB + idx];
     return v;
 }
 
@@ -119,6 +129,13 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
             sum += fabs(d0 + a2 * dt2_diag(ip, nx)) + spread;
             if (ip + 1 < nx) sum += fabs(a1);
             if (ip + 2 < nx) sum += fabs(a2);
+            // chain terms C (x) diag(alpha) Dt diag(beta): column ip has entries
+            // alpha_{ip -+ 1} beta_ip in rows ip -+ 1
+            if (b >= -a.RW && b <= a.RW) {
+                const double nb = (ip - 1 >= 0 ? 1.0 : 0.0) + (ip + 1 < nx ? 1.0 : 0.0);
+                for (int f = 0; f < a.NC; ++f)
+                    sum += fabs(coeff_c(a, c, j, f * wl + b + a.RW)) * a.cstat[4 * f] * nb;
+            }
         }
         best = fmax(best, sum);
         if (sum != sum) best = sum;   // keep NaN visible
@@ -170,6 +187,12 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
                 if (e == o0 + a.R0) v -= mu;
             }
             reinterpret_cast<double*>(rows)[idx] = v * inv_s;
+        }
+        // chain section (no trace shift: the chains have no diagonal)
+        double* crows = reinterpret_cast<double*>(rows) + (size_t)a.nv_pad * a.NBP;
+        for (int idx = t; idx < a.nv_pad * a.NCB; idx += kThreads) {
+            const int j = idx / a.NCB, e = idx % a.NCB;
+            crows[idx] = j < nv ? coeff_c(a, c, j, e) * inv_s : 0.0;
         }
         return;
     }
@@ -230,6 +253,10 @@ hipError_t launch_assemble(const mg_ops* ops, const double* coef, int64_t P, int
     a.RW = ops->RW;
     a.xstat = ops->ND > 0 ? ops->xdiag_dev + (size_t)ops->ND * ops->grid.nx : nullptr;
     a.use24 = tol >= 0x1p-24 ? 1 : 0;
+    a.NC = ops->NC;
+    a.NCB = ops->NCB;
+    a.basis_c = ops->basis_dev + (size_t)MG_NBASIS * ops->nv_pad * ops->NBP;
+    a.cstat = ops->NC > 0 ? mg_cstat_dev(ops) : nullptr;
     const int64_t blocks = P * K;
     hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, s, a);
     return hipGetLastError();

@@ -66,6 +66,8 @@ struct CoopArgs {
     int32_t* stats;
     int32_t* flags;
     const double* xdiag;   // x vectors of the x-dependent factors [ND][nx]
+    const double* xchain;  // chain vectors [NC][alpha, beta][nx]
+    int nv_pad;            // table rows before the chain section
     XArea x;
 };
 
@@ -300,11 +302,13 @@ constexpr bool xa_in_lds() {
     return ND > 0 && sizeof(T) == 8;
 }
 
-// LDS: halo | abort word (16 bytes) | x vectors [ND][64*PX] (when in LDS)
-template <int PX, int NW, int RH, int ND, class T>
+// LDS: halo | abort word (16 bytes) | x vectors [ND][64*PX] (when in LDS) |
+// chain vectors [NC][2][64*PX]
+template <int PX, int NW, int RH, int ND, class T, int NC = 0>
 constexpr size_t coop_lds_bytes() {
     return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + 16 +
-           (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX * sizeof(T) : 0);
+           (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX * sizeof(T) : 0) +
+           (size_t)NC * 2 * 64 * PX * sizeof(T);
 }
 
 // The x vectors at this lane's points (zero beyond nx), in registers or in LDS
@@ -346,11 +350,13 @@ struct XVec<PX, ND, true, T> {
     }
 };
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND,
+          int NC>
 __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
+    constexpr int NCB = NC * (2 * MG_XDIAG_RADIUS + 1);
     constexpr int RW = NW * RJ;
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
@@ -362,19 +368,32 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     const int row0 = g * RW + w * RJ;                 // first global row of this wave
     const int nrows = min(RJ, max(0, nv - row0));
     // the x vectors of the x-dependent factors at this lane's points
-    const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(
-        a.xdiag, lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T), lane, nx);
+    T* xl = lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T);
+    const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(a.xdiag, xl, lane, nx);
+    // chain vectors [NC][alpha, beta][64*PX] in LDS after the x vectors
+    T* cvl = xl + (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX : 0);
+    if constexpr (NC > 0) {
+        for (int idx = threadIdx.x; idx < NC * 2 * 64 * PX; idx += 64 * NW) {
+            const int kh = idx / (64 * PX), i = idx % (64 * PX);
+            cvl[idx] = i < nx ? (T)a.xchain[(size_t)kh * nx + i] : T(0);
+        }
+    }
+    auto cvec = [&](int k, int h, int q) -> T { return cvl[(k * 2 + h) * 64 * PX + lane * PX + q]; };
     __syncthreads();
 
     // one application of the operator to this wave's rows, in place
     auto apply_term = [&](T (&d)[RJ][PX], const T (&top)[RH][PX], const T (&bot)[RH][PX],
-                          auto coef, auto emit) {
+                          auto coef, auto ccoef, auto emit) {
         if constexpr (ND == 0)
             apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef, lane, nx,
                                                                   emit);
-        else
+        else if constexpr (NC == 0)
             apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
                 d, top, bot, coef, xa, lane, nx, emit);
+        else
+            apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T,
+                            decltype(coef), decltype(xa), decltype(emit), NC, decltype(ccoef),
+                            decltype(cvec)>(d, top, bot, coef, xa, lane, nx, emit, ccoef, cvec);
     };
 
     for (int64_t p = grp; p < a.P && !cg.aborted; p += a.x.ngroups) {
@@ -401,6 +420,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
             pflag |= tv.flag();
             const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
             auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
+            // chain section of the table (after the nv_pad main rows)
+            const T* crows = tv.rows<T>() + (size_t)a.nv_pad * NBP + (size_t)row0 * NCB;
+            auto ccoef = [&](int r, int e) -> T { return crows[r * NCB + e]; };
             int terms = 0;
             for (int sub = 0; sub < s && !cg.aborted; ++sub) {
                 T d[RJ][PX];
@@ -461,7 +483,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                                 mf = max_abs(mf, t);
                             }
                         };
-                        apply_term(d, top, bot, coef, emit);
+                        apply_term(d, top, bot, coef, ccoef, emit);
                         mc = wave_max(mc);
                     } else {
                         fj /= (T)j;
@@ -473,7 +495,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                                 mf = max_abs(mf, F[r][q]);
                             }
                         };
-                        apply_term(d, top, bot, coef, emit);
+                        apply_term(d, top, bot, coef, ccoef, emit);
                         mc = wave_max(mc) * fj;
                     }
                     mf = wave_max(mf);
@@ -861,14 +883,15 @@ bool pick_coop_shape(int nx, CoopShape& sh) {
     return false;
 }
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND,
+          int NC = 0>
 hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     *nw = NW;
     *rows = NW * RJ;
-    *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND>;
-    *lds = coop_lds_bytes<PX, NW, RH, ND, T>();
+    *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND, NC>;
+    *lds = coop_lds_bytes<PX, NW, RH, ND, T, NC>();
     return hipSuccess;
 }
 
@@ -990,6 +1013,21 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, co
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
     const int* R = ops->R;
     const int qmax = ops->qmax;
+    if (kind == CoopKind::Expmv && ops->NC > 0) {
+        // chain terms: FP64, four x-factors, two chains, the order-2 band shape,
+        // the FP64 x-factor workgroup shapes
+        if (precision != MG_FP64 || ops->ND != MG_MAX_XDIAG || ops->NC != MG_MAX_XCHAIN ||
+            !(R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1))
+            return hipErrorInvalidValue;
+        const bool full = ops->grid.nx == 64 * sh.PX;
+#define MG_CHAIN_INFO(PX, RJ, NW, FX)                                                            \
+    return coop_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, MG_MAX_XCHAIN>(      \
+        fn, lds, nw, rows);
+        if (sh.PX == 4) { if (full) { MG_CHAIN_INFO(4, 16, 4, true) } else { MG_CHAIN_INFO(4, 16, 4, false) } }
+        if (sh.PX == 8) { if (full) { MG_CHAIN_INFO(8, 8, 4, true) } else { MG_CHAIN_INFO(8, 8, 4, false) } }
+#undef MG_CHAIN_INFO
+        return hipErrorInvalidValue;
+    }
     if (kind == CoopKind::Euler) {
         if (precision != MG_FP64) return hipErrorInvalidValue;
 #define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
@@ -1124,6 +1162,8 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
     a.stats = stats;
     a.flags = flags;
     a.xdiag = ops->xdiag_dev;
+    a.xchain = ops->NC > 0 ? mg_xchain_dev(ops) : nullptr;
+    a.nv_pad = ops->nv_pad;
     a.x = xarea_of(xarea, plan);
     const int nfl = plan.ngroups * plan.G;
     hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.x.fl, nfl,

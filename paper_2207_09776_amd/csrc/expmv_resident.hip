@@ -118,21 +118,25 @@ constexpr FactorTables make_factor_tables() {
 __constant__ FactorTables kFactors = make_factor_tables();
 static_assert(MG_THETA_MMAX < 64, "factor tables too short");
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND, int NC>
 __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, double tol,
-    int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag) {
+    int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag,
+    const double* __restrict__ xchain) {
     using T = double;
     using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
+    constexpr int NCB = NC * (2 * MG_XDIAG_RADIUS + 1);
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
     T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);   // [2][NW][2] term norms
     T* red2 = red + 2 * NW * 2;                                 // [2][NW] state norms
     int* sflag = reinterpret_cast<int*>(red2 + 2 * NW);
+    // chain vectors [NC][alpha, beta][64*PX] after the flag word (16 bytes)
+    T* cvl = red2 + 2 * NW + 2;
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -152,6 +156,15 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
             const int i = lane * PX + q;
             xa[t][q] = (ND > 0 && i < nx) ? (T)xdiag[(size_t)t * nx + i] : T(0);
         }
+    // chain vectors at every lane's points into LDS (zero beyond nx; read
+    // after the first barrier of the term loop)
+    if constexpr (NC > 0) {
+        for (int idx = threadIdx.x; idx < NC * 2 * 64 * PX; idx += 64 * NW) {
+            const int kh = idx / (64 * PX), i = idx % (64 * PX);
+            cvl[idx] = i < nx ? xchain[(size_t)kh * nx + i] : 0.0;
+        }
+    }
+    auto cvec = [&](int k, int h, int q) -> T { return cvl[(k * 2 + h) * 64 * PX + lane * PX + q]; };
 
     T F[RJ][PX];
     {
@@ -188,6 +201,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
         const double es = tv.es();
         pflag |= tv.flag();
         const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
+        // chain section: after the NW*RJ main rows (the table's padded rows)
+        const T* crows = tv.rows<T>() + (size_t)NW * RJ * NBP + (size_t)row0 * NCB;
         int terms = 0;
         for (int sub = 0; sub < s; ++sub) {
             // the Taylor terms alternate between A and B (no copies between terms)
@@ -218,14 +233,23 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                 auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
                 const T fj = kFactors.inv_fact[j];   // 1/j!
                 T mc = 0, mf = 0;
-                apply_rows_any<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, T>(
-                    in, out, top, bot, fb, ft, coef, xa, lane, nx, [&](int r, T (&y)[PX]) {
+                auto emit = [&](int r, T (&y)[PX]) {
 #pragma unroll
-                        for (int q = 0; q < PX; ++q) {
-                            F[r][q] = fma(y[q], fj, F[r][q]);
-                            mc = max_abs(mc, y[q]);
-                        }
-                    });
+                    for (int q = 0; q < PX; ++q) {
+                        F[r][q] = fma(y[q], fj, F[r][q]);
+                        mc = max_abs(mc, y[q]);
+                    }
+                };
+                if constexpr (NC > 0) {
+                    auto ccoef = [crows](int r, int e) -> T { return crows[r * NCB + e]; };
+                    apply_rows_any<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, T, NDX, decltype(coef),
+                                   decltype(fb), decltype(ft), decltype(emit), NC,
+                                   decltype(ccoef), decltype(cvec)>(
+                        in, out, top, bot, fb, ft, coef, xa, lane, nx, emit, ccoef, cvec);
+                } else {
+                    apply_rows_any<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, T>(
+                        in, out, top, bot, fb, ft, coef, xa, lane, nx, emit);
+                }
                 if (rule.wantf) {
 #pragma unroll
                     for (int r = 0; r < RJ; ++r)
@@ -605,21 +629,26 @@ bool pick_shape(int nx, int nv, Shape& sh) {
     return false;
 }
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND, int NC>
 hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P, int K,
                      const double* u0, int bc, double* uT, double tol, int precision,
                      int32_t* stats, int32_t* flags, hipStream_t s) {
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     // the tables must have the row layout the kernel reads
-    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>()) return hipErrorInvalidValue;
+    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>() || ops->NC != NC ||
+        (NC > 0 && ops->nv_pad != NW * RJ))
+        return hipErrorInvalidValue;
     if (precision == MG_FP64) {
-        constexpr size_t lds = resident_lds_bytes<PX, NW, RH, double>();
-        auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
+        constexpr size_t lds = resident_lds_bytes<PX, NW, RH, double>() +
+                               (size_t)NC * 2 * 64 * PX * sizeof(double);
+        auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND, NC>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables, tbytes, K,
                            ops->grid.nx, ops->grid.nv, u0, bc, uT, tol, stats, flags,
-                           ops->xdiag_dev);
+                           ops->xdiag_dev, NC > 0 ? mg_xchain_dev(ops) : nullptr);
+    } else if constexpr (NC > 0) {
+        return hipErrorInvalidValue;   // chains: FP64 only
     } else {
         constexpr size_t lds =
             f32c_stages_rows<PX>()
@@ -657,25 +686,46 @@ hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE,
 // v-dependent coefficients.  B and A (Euler) only carry Dt^0 and Dt^1.
 #define MG_FOR_SHAPE(PX, RJ, NW, FULLX, CALL)                                                  \
     if (ops->ND == 3) {                                                                        \
-        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 3); \
-        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 3); \
+        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 3, 0); \
+        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 3, 0); \
         return hipErrorInvalidValue;                                                           \
     }                                                                                          \
     if (ops->ND == MG_MAX_XDIAG) {                                                             \
-        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, MG_MAX_XDIAG); \
-        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG); \
+        if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, MG_MAX_XDIAG, 0); \
+        if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG, 0); \
         return hipErrorInvalidValue;                                                           \
     }                                                                                          \
     if (ops->ND > 0) return hipErrorInvalidValue;                                              \
-    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 0); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 0); \
-    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, 0); \
-    if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX, 0); \
+    if (R[0] == 1 && R[1] == 0 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 1, 0, 0, 1, FULLX, 0, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1) return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, 0, 0); \
+    if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, 0, 0); \
+    if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX, 0, 0); \
+    return hipErrorInvalidValue;
+// operators with chain terms (x-dependent noise meeting D^x): four x-factors,
+// two chains, the order-2 band shape (FP64)
+#define MG_FOR_SHAPE_CHAINS(PX, RJ, NW, FULLX, CALL)                                           \
+    if (ops->ND == MG_MAX_XDIAG && ops->NC == MG_MAX_XCHAIN && R[0] == 2 && R[1] == 1 &&       \
+        R[2] == 0 && qmax == 1)                                                                \
+        return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG, MG_MAX_XCHAIN);               \
     return hipErrorInvalidValue;
 
 #define MG_SHAPE_CASE(SPX, SRJ, SNW, CALL)                                                     \
     if (sh.PX == SPX && sh.RJ == SRJ && sh.NW == SNW) {                                        \
         if (full) { MG_FOR_SHAPE(SPX, SRJ, SNW, true, CALL) } else { MG_FOR_SHAPE(SPX, SRJ, SNW, false, CALL) } \
+    }
+#define MG_SHAPE_CASE_CHAINS(SPX, SRJ, SNW, CALL)                                              \
+    if (sh.PX == SPX && sh.RJ == SRJ && sh.NW == SNW) {                                        \
+        if (full) { MG_FOR_SHAPE_CHAINS(SPX, SRJ, SNW, true, CALL) } else { MG_FOR_SHAPE_CHAINS(SPX, SRJ, SNW, false, CALL) } \
+    }
+#define MG_DISPATCH_CHAINS(CALL)                                                               \
+    {                                                                                          \
+        const bool full = (nx == 64 * sh.PX);                                                  \
+        MG_SHAPE_CASE_CHAINS(1, 16, 2, CALL)                                                   \
+        MG_SHAPE_CASE_CHAINS(1, 16, 4, CALL)                                                   \
+        MG_SHAPE_CASE_CHAINS(1, 16, 8, CALL)                                                   \
+        MG_SHAPE_CASE_CHAINS(2, 16, 4, CALL)                                                   \
+        MG_SHAPE_CASE_CHAINS(2, 16, 8, CALL)                                                   \
+        return hipErrorInvalidValue;                                                           \
     }
 // the default shapes (pick_shape)
 #define MG_DISPATCH(CALL)                                                                      \
@@ -752,9 +802,10 @@ hipError_t launch_expmv_resident(const mg_ops* ops, const char* tables, size_t t
     if (dry_run) return hipSuccess;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-#define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX, ND)                                   \
-    run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX, ND>(ops, tables, tbytes, P, K, u0, u0_broadcast, uT, \
-                                              tol, precision, stats, flags, s)
+#define MG_CALL_EXPMV(PX, RJ, NW, R0, R1, R2, QM, FX, ND, NC)                               \
+    run_expmv<PX, RJ, NW, R0, R1, R2, QM, FX, ND, NC>(ops, tables, tbytes, P, K, u0, u0_broadcast, \
+                                                  uT, tol, precision, stats, flags, s)
+    if (ops->NC > 0) MG_DISPATCH_CHAINS(MG_CALL_EXPMV)   // chains: the default shapes
     MG_DISPATCH_TUNED(MG_CALL_EXPMV)
 #undef MG_CALL_EXPMV
 }
@@ -767,7 +818,7 @@ hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const 
     if (dry_run) return hipSuccess;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-#define MG_CALL_EULER(PX, RJ, NW, R0, R1, R2, QM, FX, ND) \
+#define MG_CALL_EULER(PX, RJ, NW, R0, R1, R2, QM, FX, ND, NC) \
     run_euler<PX, RJ, NW, R0, R1, R2, 1, FX, ND>(ops, u, P, dWE, NE, dt, flags, s)
     MG_DISPATCH(MG_CALL_EULER)
 #undef MG_CALL_EULER

@@ -189,6 +189,41 @@ __device__ inline void apply_operator(In din, Coef coef, int lane, int nx, T (&o
     }
 }
 
+// Default for the chain-term accessors of the x-factor operators (no chains).
+struct NoChains {
+    template <class... A>
+    __device__ double operator()(A...) const { return 0.0; }
+};
+
+// Chain terms C_k (x) diag(alpha_k) Dt diag(beta_k) of row r, added to y:
+// alpha_k * Dt(beta_k * sum_b C_k[r][b] d(r - RC + b)).  `ccoef(r, e)` is the
+// coefficient e of row r in the chain section of the table (NC bands of
+// 2 RC + 1), `cvec(k, h, q)` the chain vector h (0: alpha, 1: beta) of chain k
+// at this lane's point q (zero beyond nx, so the x edge needs no branch).
+template <int PX, int NC, int RC, class T, class Din, class CCoef, class CVec>
+__device__ inline void add_chains(int r, T (&y)[PX], Din din, CCoef ccoef, CVec cvec) {
+    constexpr int WL = 2 * RC + 1;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        T c[WL];
+#pragma unroll
+        for (int b = 0; b < WL; ++b) c[b] = ccoef(r, k * WL + b);
+        T w[PX];
+#pragma unroll
+        for (int q = 0; q < PX; ++q) w[q] = c[0] * din(r - RC, q);
+#pragma unroll
+        for (int b = 1; b < WL; ++b)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) w[q] = fma(c[b], din(r - RC + b, q), w[q]);
+#pragma unroll
+        for (int q = 0; q < PX; ++q) w[q] *= cvec(k, 1, q);
+        T e[PX];
+        dt_apply<PX, T>(w, e);
+#pragma unroll
+        for (int q = 0; q < PX; ++q) y[q] = fma(cvec(k, 0, q), e[q], y[q]);
+    }
+}
+
 // One application of the banded-Kronecker operator to the RJ rows of this
 // wave, in place: d holds the input rows, top/bot the RH halo rows above and
 // below.  Row r of the result y is handed to `emit(r, y)`, which returns the
@@ -286,10 +321,11 @@ __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
 // apply_inplace overwrites d[r - RH], so the rows r - RW .. r + RW read here
 // are still the input (RW <= RH).
 template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, int RW,
-          class T, class Coef, class XA, class Emit>
+          class T, class Coef, class XA, class Emit, int NC = 0, class CCoef = NoChains,
+          class CVec = NoChains>
 __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
                                        const T (&bot)[RH][PX], Coef coef, XA xa, int lane, int nx,
-                                       Emit emit) {
+                                       Emit emit, CCoef ccoef = CCoef{}, CVec cvec = CVec{}) {
     constexpr int NBM = Bands<R0, R1, R2, QMAX>::NB;
     constexpr int WL = 2 * RW + 1;
     static_assert(RW <= RH, "halo narrower than the x-dependent factors");
@@ -317,6 +353,7 @@ __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
 #pragma unroll
                 for (int q = 0; q < PX; ++q) y[q] = fma(xa(t, q), z[q], y[q]);
             }
+            if constexpr (NC > 0) add_chains<PX, NC, RW, T>(r, y, din, ccoef, cvec);
             emit(r, y);
         });
 }
@@ -478,12 +515,14 @@ __device__ inline void apply_split(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&t
 // a_t at this lane's points in xa.  The W bands follow the V bands in the table
 // row (NBM coefficients); their coefficients are requested at the start of the
 // row.  RH must cover RW.
+
 template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, int RW,
-          class T, class Coef, class FetchBot, class FetchTop, class Emit>
+          class T, class Coef, class FetchBot, class FetchTop, class Emit, int NC = 0,
+          class CCoef = NoChains, class CVec = NoChains>
 __device__ inline void apply_split_x(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&top)[RH][PX],
                                      T (&bot)[RH][PX], FetchBot fetch_bot, FetchTop fetch_top,
                                      Coef coef, const T (&xa)[ND][PX], int lane, int nx,
-                                     Emit emit) {
+                                     Emit emit, CCoef ccoef = CCoef{}, CVec cvec = CVec{}) {
     constexpr int NBM = Bands<R0, R1, R2, QMAX>::NB;
     constexpr int WL = 2 * RW + 1;
     static_assert(RW <= RH, "halo narrower than the x-dependent factors");
@@ -524,6 +563,7 @@ __device__ inline void apply_split_x(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (
 #pragma unroll
                 for (int q = 0; q < PX; ++q) y[q] = fma(xa[t][q], z[q], y[q]);
             }
+            if constexpr (NC > 0) add_chains<PX, NC, RW, T>(r, y, din, ccoef, cvec);
             emit(r, y);
         });
 }
@@ -545,16 +585,19 @@ constexpr int table_stride() {
 
 // apply_split, or apply_split_x when the operator has x-dependent factors.
 template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, class T,
-          int NDX, class Coef, class FetchBot, class FetchTop, class Emit>
+          int NDX, class Coef, class FetchBot, class FetchTop, class Emit, int NC = 0,
+          class CCoef = NoChains, class CVec = NoChains>
 __device__ inline void apply_rows_any(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (&top)[RH][PX],
                                       T (&bot)[RH][PX], FetchBot fb, FetchTop ft, Coef coef,
-                                      const T (&xa)[NDX][PX], int lane, int nx, Emit emit) {
+                                      const T (&xa)[NDX][PX], int lane, int nx, Emit emit,
+                                      CCoef ccoef = CCoef{}, CVec cvec = CVec{}) {
     if constexpr (ND == 0)
         apply_split<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, out, top, bot, fb, ft, coef, lane, nx,
                                                             emit);
     else
-        apply_split_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
-            d, out, top, bot, fb, ft, coef, xa, lane, nx, emit);
+        apply_split_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T, Coef, FetchBot,
+                      FetchTop, Emit, NC, CCoef, CVec>(d, out, top, bot, fb, ft, coef, xa, lane,
+                                                      nx, emit, ccoef, cvec);
 }
 
 // LDS halo layout: halo[parity][wave + 1][slot][64*PX] for waves -1 .. NW; the

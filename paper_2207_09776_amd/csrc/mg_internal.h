@@ -28,7 +28,8 @@
 constexpr int MG_NBASIS = 6;
 constexpr int MG_HDR = 8;          // table header entries (doubles)
 constexpr int MG_MAX_XDIAG = 4;    // most x-dependent factors the kernels take
-constexpr int MG_XDIAG_RADIUS = 2; // band radius of their v factors
+constexpr int MG_XDIAG_RADIUS = 2; // band radius of their v factors (and of the chain factors)
+constexpr int MG_MAX_XCHAIN = 2;   // chains diag(a) D^x diag(b) the kernels take
 
 struct mg_ops {
     mg_grid grid;
@@ -39,12 +40,17 @@ struct mg_ops {
     int nactive;                   // basis matrices used by `order` (2, 4 or 6)
     int nv_pad;                    // table rows: nv rounded up to the kernel's rows (zeros)
     int ND = 0, RW = 0;            // x-dependent factors and their band radius
-    // basis tables, host copy and device copy: [MG_NBASIS][nv_pad][NBP]
+    int NC = 0, NCB = 0;           // chain terms C (x) diag(a) D^x diag(b) (0 or
+                                   // MG_MAX_XCHAIN) and their coefficients per row
+                                   // (NC bands of radius MG_XDIAG_RADIUS)
+    // basis tables, host copy and device copy: [MG_NBASIS][nv_pad][NBP], then
+    // the chain section [MG_NBASIS][nv_pad][NCB]
     std::vector<double> basis_host;
     double* basis_dev = nullptr;
-    // x vectors a_t [ND][nx] and per factor {sum, midpoint, half-width, 0}
-    std::vector<double> xdiag_host, xstat_host;
-    double* xdiag_dev = nullptr;   // xdiag, then xstat, in one allocation
+    // x vectors a_t [ND][nx] and per factor {sum, midpoint, half-width, 0};
+    // chain vectors [NC][alpha, beta][nx] and per chain {max|alpha| max|beta|, 0, 0, 0}
+    std::vector<double> xdiag_host, xstat_host, xchain_host, cstat_host;
+    double* xdiag_dev = nullptr;   // xdiag, xstat, xchain, cstat in one allocation
     int device = 0;
     // register-resident kernel shape (PX, RJ, NW) recorded by the autotuner
     // per precision (FP64, FP32C); zeros: the default shape
@@ -57,11 +63,24 @@ struct mg_ops {
 //                   [f64 ||Y - mu I||_1] [int32 flag, pad] [2 x f64 reserved]
 //   then nv_pad rows of NBP coefficients of (Y - mu I)/s, FP64 (MG_FP64) or
 //   FP32 rounded from FP64 with each band's rounding residual in its centre
-//   entry (MG_FP32C); records are 64-byte aligned.
+//   entry (MG_FP32C), then nv_pad rows of the NCB chain coefficients (FP64
+//   only); records are 64-byte aligned.
 inline size_t mg_table_bytes(const mg_ops* ops, int precision) {
     const size_t elem = precision == MG_FP32C ? 4 : 8;
-    size_t b = 64 + (size_t)ops->nv_pad * ops->NBP * elem;
+    size_t b = 64 + (size_t)ops->nv_pad * (ops->NBP + ops->NCB) * elem;
     return (b + 63) & ~(size_t)63;
+}
+
+// device copies of the per-factor statistics and of the chain vectors, which
+// follow the x vectors in the xdiag_dev allocation
+inline const double* mg_xstat_dev(const mg_ops* ops) {
+    return ops->xdiag_dev + ops->xdiag_host.size();
+}
+inline const double* mg_xchain_dev(const mg_ops* ops) {
+    return ops->xdiag_dev + ops->xdiag_host.size() + ops->xstat_host.size();
+}
+inline const double* mg_cstat_dev(const mg_ops* ops) {
+    return mg_xchain_dev(ops) + ops->xchain_host.size();
 }
 
 // error state (thread local, defined in api.hip)

@@ -17,9 +17,13 @@
 // is written exactly (to rounding) as a short sum sum_t b_t(v) a_t(x) by a
 // cross decomposition with complete pivoting, so diag(vec Z) = sum_t
 // diag(b_t) (x) diag(a_t): the operators gain terms W (x) diag(a) next to the
-// V_q (x) D^q terms.  Products stay of that form as long as no power of D^x
-// meets a non-constant diag(a) (diag(a) diag(b) = diag(ab)); otherwise the
-// build reports the combination as unsupported.
+// V_q (x) D^q terms.  Where D^x meets such a factor once in a product (the
+// commutators of eq. (MagnusFormulas) with x-dependent noise through d/dv,
+// as in eq. (coeffsLangevinVar)), the x part is a chain
+// diag(alpha) D^x diag(beta) (one of alpha, beta may be the unit vector):
+// the operators gain terms C (x) diag(alpha) D^x diag(beta).  Products that
+// would need a second D^x on a chain, or a chain times a chain, are reported
+// as unsupported.
 
 #include <algorithm>
 #include <cmath>
@@ -111,10 +115,14 @@ struct XReg {
 };
 
 // sum_{q=0..2} V[q] (x) (D^x)^q + sum_k W[k] (x) diag(xreg.vecs[id[k]])
+//   + sum_k C[k] (x) diag(a_k) D^x diag(b_k)   (a_k = vecs[ca[k]], b_k =
+//   vecs[cb[k]], index -1: the unit vector)
 struct KOp {
     Band V[3];
     std::vector<Band> W;
     std::vector<int> id;
+    std::vector<Band> C;
+    std::vector<int> ca, cb;
     explicit KOp(int nv) { for (auto& b : V) b = band_zero(nv); }
     void add_w(int xid, const Band& B) {
         for (size_t k = 0; k < id.size(); ++k)
@@ -125,7 +133,28 @@ struct KOp {
         id.push_back(xid);
         W.push_back(B);
     }
+    void add_c(int ia, int ib, const Band& B) {
+        for (size_t k = 0; k < ca.size(); ++k)
+            if (ca[k] == ia && cb[k] == ib) {
+                C[k] = band_axpby(1.0, C[k], 1.0, B);
+                return;
+            }
+        ca.push_back(ia);
+        cb.push_back(ib);
+        C.push_back(B);
+    }
 };
+
+// registry id of the pointwise product of two x vectors (-1: unit)
+int xmul(XReg& xr, int ia, int ib) {
+    if (ia < 0) return ib;
+    if (ib < 0) return ia;
+    const std::vector<double>& a = xr.vecs[ia];
+    const std::vector<double>& b = xr.vecs[ib];
+    std::vector<double> ab(a.size());
+    for (size_t i = 0; i < a.size(); ++i) ab[i] = a[i] * b[i];
+    return xr.find_or_add(ab);
+}
 
 // Product of two factored operators; false (with a reason) when a power of
 // D^x meets a non-constant diagonal x-factor, which this form cannot hold.
@@ -140,27 +169,65 @@ bool kop_mul(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
             if (p + q > 2) { why = "x-derivative power above 2 in the Magnus basis"; return false; }
             Z.V[p + q] = band_axpby(1.0, Z.V[p + q], 1.0, P);
         }
+    const char* deep = "an x derivative meets an x-dependent coefficient more than once in the "
+                       "Magnus basis (order 3 with x-dependent noise)";
+    // (V (x) D^p)(W (x) diag(a)): diag for p = 0, the chain D diag(a) for p = 1
     for (size_t k = 0; k < Y.W.size(); ++k)
         for (int p = 0; p < 3; ++p) {
             if (band_is_zero(X.V[p]) || band_is_zero(Y.W[k])) continue;
             Band P = band_mul(X.V[p], Y.W[k]);
             if (band_is_zero(P)) continue;
-            if (p > 0) {
-                why = "an x derivative meets an x-dependent coefficient in the Magnus basis";
-                return false;
-            }
-            Z.add_w(Y.id[k], P);
+            if (p > 1) { why = deep; return false; }
+            if (p == 0) Z.add_w(Y.id[k], P);
+            else Z.add_c(-1, Y.id[k], P);
         }
+    // (V (x) D^p) chain: only p = 0
+    for (size_t k = 0; k < Y.C.size(); ++k)
+        for (int p = 0; p < 3; ++p) {
+            if (band_is_zero(X.V[p]) || band_is_zero(Y.C[k])) continue;
+            Band P = band_mul(X.V[p], Y.C[k]);
+            if (band_is_zero(P)) continue;
+            if (p > 0) { why = deep; return false; }
+            Z.add_c(Y.ca[k], Y.cb[k], P);
+        }
+    // chain (V (x) D^q): only q = 0; chain (W (x) diag(b)) = chain with beta b
+    for (size_t k = 0; k < X.C.size(); ++k) {
+        for (int q = 0; q < 3; ++q) {
+            if (band_is_zero(X.C[k]) || band_is_zero(Y.V[q])) continue;
+            Band P = band_mul(X.C[k], Y.V[q]);
+            if (band_is_zero(P)) continue;
+            if (q > 0) { why = deep; return false; }
+            Z.add_c(X.ca[k], X.cb[k], P);
+        }
+        for (size_t m = 0; m < Y.W.size(); ++m) {
+            if (band_is_zero(X.C[k]) || band_is_zero(Y.W[m])) continue;
+            Band P = band_mul(X.C[k], Y.W[m]);
+            if (band_is_zero(P)) continue;
+            Z.add_c(X.ca[k], xmul(xr, X.cb[k], Y.id[m]), P);
+        }
+        for (size_t m = 0; m < Y.C.size(); ++m) {
+            if (band_is_zero(X.C[k]) || band_is_zero(Y.C[m])) continue;
+            if (band_is_zero(band_mul(X.C[k], Y.C[m]))) continue;
+            why = deep;
+            return false;
+        }
+    }
     for (size_t k = 0; k < X.W.size(); ++k) {
+        // (W (x) diag(a))(V (x) D^q): diag for q = 0, the chain diag(a) D for q = 1
         for (int q = 0; q < 3; ++q) {
             if (band_is_zero(X.W[k]) || band_is_zero(Y.V[q])) continue;
             Band P = band_mul(X.W[k], Y.V[q]);
             if (band_is_zero(P)) continue;
-            if (q > 0) {
-                why = "an x derivative meets an x-dependent coefficient in the Magnus basis";
-                return false;
-            }
-            Z.add_w(X.id[k], P);
+            if (q > 1) { why = deep; return false; }
+            if (q == 0) Z.add_w(X.id[k], P);
+            else Z.add_c(X.id[k], -1, P);
+        }
+        // (W (x) diag(a)) chain = chain with alpha a * alpha
+        for (size_t m = 0; m < Y.C.size(); ++m) {
+            if (band_is_zero(X.W[k]) || band_is_zero(Y.C[m])) continue;
+            Band P = band_mul(X.W[k], Y.C[m]);
+            if (band_is_zero(P)) continue;
+            Z.add_c(xmul(xr, X.id[k], Y.ca[m]), Y.cb[m], P);
         }
         for (size_t m = 0; m < Y.W.size(); ++m) {
             if (band_is_zero(X.W[k]) || band_is_zero(Y.W[m])) continue;
@@ -185,6 +252,9 @@ bool kop_comm(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) 
     for (int q = 0; q < 3; ++q) Z.V[q] = band_axpby(1.0, XY.V[q], -1.0, YX.V[q]);
     for (size_t k = 0; k < XY.W.size(); ++k) Z.add_w(XY.id[k], XY.W[k]);
     for (size_t k = 0; k < YX.W.size(); ++k) Z.add_w(YX.id[k], band_axpby(-1.0, YX.W[k], 0.0, YX.W[k]));
+    for (size_t k = 0; k < XY.C.size(); ++k) Z.add_c(XY.ca[k], XY.cb[k], XY.C[k]);
+    for (size_t k = 0; k < YX.C.size(); ++k)
+        Z.add_c(YX.ca[k], YX.cb[k], band_axpby(-1.0, YX.C[k], 0.0, YX.C[k]));
     out = Z;
     return true;
 }
@@ -336,12 +406,38 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         wa[k] = m;
     }
     std::vector<int> used(xr.vecs.size(), 0);
+    // chain terms: weight max|alpha| max|beta| / dx, and the distinct chains
+    // the active matrices use
+    auto xmax = [&](int id) { return id < 0 ? 1.0 : wa[id]; };
+    std::vector<std::pair<int, int>> chains;
+    auto chain_slot = [&](int ia, int ib) {
+        for (size_t c = 0; c < chains.size(); ++c)
+            if (chains[c].first == ia && chains[c].second == ib) return (int)c;
+        chains.push_back({ia, ib});
+        return (int)chains.size() - 1;
+    };
+    int RC = 0;
     for (int l = 0; l < MG_NBASIS; ++l) {
         double mx = 0.0;
         for (int q = 0; q < 3; ++q)
             for (double v : M[l].V[q].a) mx = std::max(mx, std::fabs(v) * wq[q]);
         for (size_t k = 0; k < M[l].W.size(); ++k)
             for (double v : M[l].W[k].a) mx = std::max(mx, std::fabs(v) * wa[M[l].id[k]]);
+        for (size_t k = 0; k < M[l].C.size(); ++k) {
+            const double wc = xmax(M[l].ca[k]) * xmax(M[l].cb[k]) / dx;
+            for (double v : M[l].C[k].a) mx = std::max(mx, std::fabs(v) * wc);
+        }
+        for (size_t k = 0; k < M[l].C.size(); ++k) {
+            Band& C = M[l].C[k];
+            const double wc = xmax(M[l].ca[k]) * xmax(M[l].cb[k]) / dx;
+            for (double& v : C.a)
+                if (std::fabs(v) * wc <= 1e-14 * mx) v = 0.0;
+            if (l >= nact || band_is_zero(C)) continue;
+            for (int i = 0; i < nv; ++i)
+                for (int o = -C.r; o <= C.r; ++o)
+                    if (C.get(i, i + o) != 0.0) RC = std::max(RC, std::abs(o));
+            chain_slot(M[l].ca[k], M[l].cb[k]);
+        }
         for (int q = 0; q < 3; ++q) {
             Band& V = M[l].V[q];
             for (double& v : V.a)
@@ -373,6 +469,10 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         return mg_fail(MG_EUNSUPPORTED, "more than 4 x-dependent factors in the Magnus basis");
     if (RW > MG_XDIAG_RADIUS)
         return mg_fail(MG_EUNSUPPORTED, "band radius of an x-dependent factor above 2");
+    if ((int)chains.size() > MG_MAX_XCHAIN)
+        return mg_fail(MG_EUNSUPPORTED, "more than 2 chains diag(a) D^x diag(b) in the Magnus basis");
+    if (RC > MG_XDIAG_RADIUS)
+        return mg_fail(MG_EUNSUPPORTED, "band radius of a chain factor above 2");
     // highest power of D^x with a non-zero factor among the active matrices
     int qmax = 0;
     for (int l = 0; l < nact; ++l)
@@ -388,7 +488,8 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             qmax <= kShapes[k][3])
             shape = k;
     if (shape < 0) return mg_fail(MG_EUNSUPPORTED, "Magnus basis band radius above 3");
-    if (nd > 0 && shape > 1)
+    if (!chains.empty()) shape = std::max(shape, 1);   // built for the order-2 band shape
+    if ((nd > 0 || !chains.empty()) && shape > 1)
         return mg_fail(MG_EUNSUPPORTED,
                        "x-dependent coefficients are built for band shapes up to (2,1,0) in this build");
     for (int q = 0; q < 3; ++q) R[q] = kShapes[shape][q];
@@ -399,9 +500,11 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     ops->nactive = nact;
     for (int q = 0; q < 3; ++q) ops->R[q] = R[q];
     // x-dependent factors: the kernels are built for 3 and for 4 factors
-    // (unused ones are zero; the variable-coefficient workloads use 3)
-    ops->ND = nd > 0 ? (nd <= 3 ? 3 : MG_MAX_XDIAG) : 0;
-    ops->RW = nd > 0 ? MG_XDIAG_RADIUS : 0;
+    // (unused ones are zero; the variable-coefficient workloads use 3), and
+    // with chains for 4 factors and 2 chains
+    ops->NC = chains.empty() ? 0 : MG_MAX_XCHAIN;
+    ops->ND = nd > 0 || ops->NC > 0 ? (nd <= 3 && ops->NC == 0 ? 3 : MG_MAX_XDIAG) : 0;
+    ops->RW = ops->ND > 0 ? MG_XDIAG_RADIUS : 0;
     // V2 (the Dt^2 factor) has entries in the row only where Dt^2 occurs
     const int nq = ops->qmax >= 2 ? 3 : 2;
     ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (nq == 3 ? 2 * R[2] + 1 : 0) +
@@ -424,11 +527,27 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         st[1] = 0.5 * (hi + lo);     // midpoint and half-width of the values,
         st[2] = 0.5 * (hi - lo);     // for the 1-norm bound
     }
+    // chain vectors alpha_c, beta_c [NC][2][nx] and per chain {max|alpha| max|beta|, 0, 0, 0}
+    ops->xchain_host.assign((size_t)ops->NC * 2 * nx, 0.0);
+    ops->cstat_host.assign((size_t)ops->NC * 4, 0.0);
+    for (size_t c = 0; c < chains.size(); ++c) {
+        const int ids[2] = {chains[c].first, chains[c].second};
+        double mx[2] = {0.0, 0.0};
+        for (int h = 0; h < 2; ++h)
+            for (int i = 0; i < nx; ++i) {
+                const double v = ids[h] < 0 ? 1.0 : xr.vecs[ids[h]][i];
+                ops->xchain_host[(c * 2 + h) * nx + i] = v;
+                mx[h] = std::max(mx[h], std::fabs(v));
+            }
+        ops->cstat_host[c * 4] = mx[0] * mx[1];
+    }
     // table rows are padded to the rows the kernel shape covers
     int rows = resident_rows(nx, nv);
     if (rows == 0) rows = coop_table_rows(nx, nv);
     ops->nv_pad = std::max(nv, rows);
-    ops->basis_host.assign((size_t)MG_NBASIS * ops->nv_pad * ops->NBP, 0.0);
+    // main rows [6][nv_pad][NBP], then the chain section [6][nv_pad][NCB]
+    ops->NCB = ops->NC * (2 * MG_XDIAG_RADIUS + 1);
+    ops->basis_host.assign((size_t)MG_NBASIS * ops->nv_pad * (ops->NBP + ops->NCB), 0.0);
     const double fold[3] = {1.0, 1.0 / (2.0 * dx), 1.0 / (4.0 * dx * dx)};
     for (int l = 0; l < MG_NBASIS; ++l)
         for (int j = 0; j < nv; ++j) {
@@ -443,6 +562,19 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
                 if (sl < 0) continue;
                 double* w = row + off + sl * (2 * ops->RW + 1);
                 for (int o = -ops->RW; o <= ops->RW; ++o) w[o + ops->RW] = M[l].W[k].get(j, j + o);
+            }
+            // chain bands, with the 1/(2 dx) of D^x folded in
+            double* crow = ops->basis_host.data() + (size_t)MG_NBASIS * ops->nv_pad * ops->NBP +
+                           ((size_t)l * ops->nv_pad + j) * ops->NCB;
+            for (size_t k = 0; k < M[l].C.size(); ++k) {
+                if (band_is_zero(M[l].C[k])) continue;
+                int sl = -1;
+                for (size_t c = 0; c < chains.size(); ++c)
+                    if (chains[c].first == M[l].ca[k] && chains[c].second == M[l].cb[k]) sl = (int)c;
+                if (sl < 0) continue;   // only in matrices the order does not use
+                double* w = crow + sl * (2 * MG_XDIAG_RADIUS + 1);
+                for (int o = -MG_XDIAG_RADIUS; o <= MG_XDIAG_RADIUS; ++o)
+                    w[o + MG_XDIAG_RADIUS] = M[l].C[k].get(j, j + o) / (2.0 * dx);
             }
         }
     return MG_OK;
