@@ -387,27 +387,26 @@ def run_mixed(args, w):
         g["ops"].close()
 
 
-def paper_sweep(args):
-    """Constant-coefficient experiments of Section 3 ("comparison of Magnus
-    and Euler" for d = 100, 200, 300) with the paper's parameters: a = 1.1,
-    sigma = 1/sqrt(10), [-4, 4]^2, Gaussian initial datum exp(-(xi^2+eta^2)/2)
-    (relative errors do not depend on its scale), M = 100 paths, Lebesgue
-    discretisation 1e-4 (Nf = 10^4 for T = 1), Euler with steps 1e-3 and 1e-4,
-    orders 2 and 3 with the step sizes the paper uses per d, errors Err^{d,4}
-    against the closed form.  Paths are synthetic (seed 11), not the paper's;
-    the error magnitudes and ratios are what compares, times are this GPU's."""
-    import torch
-    import paper_2207_09776_amd as mg
-    import workloads as wl
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    a, sigma, lo, hi, T, M, Nf, kappa = 1.1, 1.0 / math.sqrt(10.0), -4.0, 4.0, 1.0, 100, 10 ** 4, 4
-    steps = {100: 0.1, 200: 0.05, 300: 0.025}
-    coeffs = wl.langevin_constant(a, sigma)
-    dW = torch.from_numpy(wl.brownian_increments(11, M, Nf, T)).to(dev)
-    rows = []
+class _Sweep:
+    """Shared set-up of the paper-parameter experiments of Sections 3 and 4:
+    a = 1.1, sigma = 1/sqrt(10), [-4, 4]^2, initial datum exp(-(xi^2+eta^2)/2)
+    (relative errors do not depend on its scale), M = 100 synthetic paths,
+    T = 1, errors Err^{d,4} (kappa = 4).  Times are per path on this GPU (one
+    batch of M paths, events around the launch); the paper's are MATLAB on a
+    V100 and are context only."""
 
-    def timed(fn):
+    a, sigma, lo, hi, T, M, kappa = 1.1, 1.0 / math.sqrt(10.0), -4.0, 4.0, 1.0, 100, 4
+
+    def __init__(self):
+        import torch
+        import paper_2207_09776_amd as mg
+        import workloads as wl
+        self.torch, self.mg, self.wl = torch, mg, wl
+        self.dev = torch.device("cuda:0")
+        torch.cuda.set_device(self.dev)
+
+    def timed(self, fn):
+        torch = self.torch
         fn()                                        # warm-up (also the result)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -417,45 +416,235 @@ def paper_sweep(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1)
 
+    def increments(self, seed, Nf):
+        return self.torch.from_numpy(self.wl.brownian_increments(seed, self.M, Nf, self.T)).to(self.dev)
+
+    def coarse(self, dW, factor):
+        """The same Brownian paths sampled at every factor-th fine node."""
+        P, Nf = dW.shape
+        return dW.view(P, Nf // factor, factor).sum(-1).contiguous()
+
+    def operators(self, coeffs, d, order):
+        wl, mg = self.wl, self.mg
+        arrays = wl.sample_coefficients(coeffs, d, d, self.lo, self.hi, self.lo, self.hi)
+        try:
+            return mg.build_operators(d, d, self.lo, self.hi, self.lo, self.hi, arrays, order)
+        except mg.MagnusError as ex:
+            if ex.code == mg.MG_EUNSUPPORTED:
+                return None
+            raise
+
+    def u0(self, d):
+        wl = self.wl
+        return self.torch.from_numpy(
+            wl.gaussian_density(d, d, self.lo, self.hi, self.lo, self.hi, 1.0).reshape(-1)).to(self.dev)
+
+    def magnus(self, ops, dW, K, order, u0):
+        """(uT, flags, ms per path) of order `order` with K steps on dW."""
+        mg, torch = self.mg, self.torch
+        coef, _ = mg.iterated_integrals(dW, self.T, K, order)
+        ws = torch.empty(mg.workspace_bytes(ops, self.M, K), dtype=torch.uint8, device=self.dev)
+        uT = torch.empty((self.M, u0.numel()), dtype=torch.float64, device=self.dev)
+        out = {}
+
+        def run():
+            _, out["f"], _ = mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws)
+        ms = self.timed(run)
+        return uT, out["f"], ms / self.M
+
+    def euler(self, ops, dW, dt, u0):
+        """(u, flags, ms per path) of Euler with step dt on the fine increments dW."""
+        mg, torch = self.mg, self.torch
+        NE = int(round(self.T / dt))
+        dWE = mg.euler_increments(dW, NE)
+        u = torch.empty((self.M, u0.numel()), dtype=torch.float64, device=self.dev)
+        need = mg.euler_workspace_bytes(ops, self.M)
+        wsb = torch.empty(max(need, 1), dtype=torch.uint8, device=self.dev) if need else None
+        out = {}
+
+        def run():
+            u.copy_(u0.expand(self.M, u0.numel()))
+            out["f"] = mg.euler_step(ops, u, dWE, dt, ws=wsb)
+        ms = self.timed(run)
+        return u, out["f"], ms / self.M
+
+    def err_exact(self, ops, u, flags, pathstat):
+        mg = self.mg
+        bad = int((flags != 0).sum())
+        err = mg.error_vs_exact(ops, u, pathstat=pathstat, a=self.a, sigma=self.sigma, s0sq=1.0,
+                                T=self.T, kappa=self.kappa)
+        return self._summ(err, bad)
+
+    def err_ref(self, ops, u, flags, uref):
+        bad = int((flags != 0).sum())
+        return self._summ(self.mg.error_vs_exact(ops, u, uref=uref, kappa=self.kappa), bad)
+
+    def _summ(self, err, bad):
+        e = err.cpu().numpy()
+        finite = np.isfinite(e)
+        # a path that left the densities or overflowed makes the mean meaningless
+        mean = float("inf") if (bad or not finite.all()) else 100 * float(e.mean())
+        med = 100 * float(np.median(e[finite])) if finite.any() else float("inf")
+        return {"err_pct": mean, "median_err_pct": med, "flagged_paths": bad}
+
+
+def sweep_constant_comparison(S):
+    """Section 3, comparison with Euler-Maruyama for d = 100, 200, 300 (the
+    paper's per-d Magnus step sizes), Lebesgue discretisation 1e-4 (Nf = 10^4
+    for T = 1), errors against the closed form.  Paths: seed 11."""
+    torch, mg = S.torch, S.mg
+    coeffs = S.wl.langevin_constant(S.a, S.sigma)
+    dW = S.increments(11, 10 ** 4)
+    steps = {100: 0.1, 200: 0.05, 300: 0.025}
+    rows = []
     for d, h in steps.items():
-        K = int(round(T / h))
-        arrays = wl.sample_coefficients(coeffs, d, d, lo, hi, lo, hi)
-        u0 = torch.from_numpy(wl.gaussian_density(d, d, lo, hi, lo, hi, 1.0).reshape(-1)).to(dev)
-        _, ps = mg.iterated_integrals(dW, T, K, 2)
+        K = int(round(S.T / h))
+        u0 = S.u0(d)
+        _, ps = mg.iterated_integrals(dW, S.T, K, 2)
         res = {"d": d}
         for order in (2, 3):
-            ops = mg.build_operators(d, d, lo, hi, lo, hi, arrays, order)
-            coef, _ = mg.iterated_integrals(dW, T, K, order)
-            ws = torch.empty(mg.workspace_bytes(ops, M, K), dtype=torch.uint8, device=dev)
-            uT = torch.empty((M, d * d), dtype=torch.float64, device=dev)
-            ms = timed(lambda: mg.magnus_expmv(ops, coef, u0, uT=uT, ws=ws))
-            err = mg.error_vs_exact(ops, uT, pathstat=ps, a=a, sigma=sigma, s0sq=1.0, T=T,
-                                    kappa=kappa)
-            res[f"M{order}, {h}"] = {"err_pct": 100 * float(err.mean()), "ms_per_path": ms / M}
-            log(f"d={d} M{order} h={h}: Err {100 * float(err.mean()):.4f} %, {ms / M:.3f} ms/path")
-        ops = mg.build_operators(d, d, lo, hi, lo, hi, arrays, 2)
+            ops = S.operators(coeffs, d, order)
+            uT, fl, ms = S.magnus(ops, dW, K, order, u0)
+            res[f"M{order}, {h}"] = dict(S.err_exact(ops, uT, fl, ps), ms_per_path=ms)
+            log(f"d={d} M{order} h={h}: {res[f'M{order}, {h}']}")
+            ops.close()
+        ops = S.operators(coeffs, d, 2)
         for dt in (1e-3, 1e-4):
-            NE = int(round(T / dt))
-            dWE = mg.euler_increments(dW, NE)
-            u = torch.empty((M, d * d), dtype=torch.float64, device=dev)
-            ws = mg.euler_workspace_bytes(ops, M)
-            wsb = torch.empty(max(ws, 1), dtype=torch.uint8, device=dev) if ws else None
-            flags = {}
-
-            def run():
-                u.copy_(u0.expand(M, d * d))
-                flags["f"] = mg.euler_step(ops, u, dWE, dt, ws=wsb)
-            ms = timed(run)
-            err = mg.error_vs_exact(ops, u, pathstat=ps, a=a, sigma=sigma, s0sq=1.0, T=T,
-                                    kappa=kappa)
-            bad = int((flags["f"] != 0).sum())
-            e = float("inf") if bad else 100 * float(err.mean())
-            res[f"E, {dt:g}"] = {"err_pct": e, "ms_per_path": ms / M, "flagged_paths": bad}
-            log(f"d={d} Euler dt={dt:g}: Err {e:.4f} %, {ms / M:.3f} ms/path")
+            u, fl, ms = S.euler(ops, dW, dt, u0)
+            res[f"E, {dt:g}"] = dict(S.err_exact(ops, u, fl, ps), ms_per_path=ms)
+            log(f"d={d} Euler dt={dt:g}: {res[f'E, {dt:g}']}")
+        ops.close()
         rows.append(res)
-    print(json.dumps({"experiment": "constant-coefficient comparison, Section 3 (paper parameters)",
-                      "paths": M, "fine_increments": Nf, "kappa": kappa, "a": a, "sigma": sigma,
-                      "domain": [lo, hi], "seed": 11, "results": rows}))
+    return {"experiment": "constant coefficients, comparison with Euler (Section 3)",
+            "paths": S.M, "fine_increments": 10 ** 4, "seed": 11, "results": rows}
+
+
+# Magnus step counts for the step-size sweeps: every divisor of the fine
+# count, so that each Magnus step spans whole fine intervals
+STEP_SWEEP_NF = 12000
+STEP_SWEEP_K = (120, 100, 80, 60, 50, 40, 30, 25, 20, 16, 15, 12, 10, 8, 6, 5, 4, 3)
+
+
+def sweep_constant_steps(S):
+    """Section 3, Figure StepTest: d = 200, orders 2 and 3 over step sizes
+    h = 1/K, errors against the closed form.  Nf = 12000 (Lebesgue
+    discretisation 8.3e-5) so that K = 3..120 divide it.  Paths: seed 12."""
+    mg = S.mg
+    d = 200
+    coeffs = S.wl.langevin_constant(S.a, S.sigma)
+    dW = S.increments(12, STEP_SWEEP_NF)
+    u0 = S.u0(d)
+    rows = []
+    for order in (2, 3):
+        ops = S.operators(coeffs, d, order)
+        for K in STEP_SWEEP_K:
+            _, ps = mg.iterated_integrals(dW, S.T, K, 2)
+            uT, fl, ms = S.magnus(ops, dW, K, order, u0)
+            r = dict(S.err_exact(ops, uT, fl, ps), order=order, h=S.T / K, K=K, ms_per_path=ms)
+            log(f"steps const d={d}: {r}")
+            rows.append(r)
+        ops.close()
+    return {"experiment": "constant coefficients, step-size sweep at d = 200 (Figure StepTest)",
+            "paths": S.M, "fine_increments": STEP_SWEEP_NF, "seed": 12, "results": rows}
+
+
+def sweep_variable(S):
+    """Section 4, eq. (coeffsLangevinVar): Table errorsVar (d = 100, 200, 300;
+    Euler 1e-3 and 1e-4 and the Magnus orders at the paper's step sizes,
+    against Euler 1e-5) and Figure StepTestVar (d = 200, step-size sweep of
+    the Magnus orders against the same reference).  Fine increments at 1e-5
+    (Nf = 10^5) drive Euler; the Magnus integrals see the same paths at 1e-4
+    (every tenth node), the paper's Lebesgue discretisation.  Paths: seed 13.
+    An order the library does not build for these coefficients is reported
+    as unsupported."""
+    torch, mg = S.torch, S.mg
+    coeffs = S.wl.langevin_paper_variable(S.a, S.sigma)
+    dWf = S.increments(13, 10 ** 5)
+    dWc = S.coarse(dWf, 10)
+    steps = {100: 0.05, 200: 0.025, 300: 0.01}
+    table, sweep = [], []
+    for d, h in steps.items():
+        K = int(round(S.T / h))
+        u0 = S.u0(d)
+        ops = S.operators(coeffs, d, 2)
+        uref, flref, msref = S.euler(ops, dWf, 1e-5, u0)
+        assert int((flref != 0).sum()) == 0, "the Euler reference left the densities"
+        res = {"d": d, "E, 1e-05": {"reference": True, "ms_per_path": msref}}
+        log(f"var d={d} Euler 1e-5 reference: {msref:.3f} ms/path")
+        for dt in (1e-3, 1e-4):
+            u, fl, ms = S.euler(ops, dWf, dt, u0)
+            res[f"E, {dt:g}"] = dict(S.err_ref(ops, u, fl, uref), ms_per_path=ms)
+            log(f"var d={d} Euler dt={dt:g}: {res[f'E, {dt:g}']}")
+            del u
+        for order in (2, 3):
+            opm = S.operators(coeffs, d, order)
+            if opm is None:
+                res[f"M{order}, {h}"] = {"unsupported": True}
+                log(f"var d={d} M{order}: unsupported")
+                continue
+            uT, fl, ms = S.magnus(opm, dWc, K, order, u0)
+            res[f"M{order}, {h}"] = dict(S.err_ref(opm, uT, fl, uref), ms_per_path=ms)
+            log(f"var d={d} M{order} h={h}: {res[f'M{order}, {h}']}")
+            if d == 200:
+                for Ks in (100, 80, 50, 40, 25, 20, 16, 10):
+                    uT, fl, ms = S.magnus(opm, dWc, Ks, order, u0)
+                    r = dict(S.err_ref(opm, uT, fl, uref), order=order, h=S.T / Ks, K=Ks,
+                             ms_per_path=ms)
+                    log(f"var steps d=200: {r}")
+                    sweep.append(r)
+            opm.close()
+        ops.close()
+        table.append(res)
+    return {"experiment": "variable coefficients (Section 4): Table errorsVar and Figure "
+                          "StepTestVar, against Euler 1e-5",
+            "paths": S.M, "fine_increments": 10 ** 5, "magnus_increments": 10 ** 4, "seed": 13,
+            "table": table, "step_sweep_d200": sweep}
+
+
+def sweep_d400(S):
+    """Conclusions: constant coefficients at d = 400, order 3 with h = 0.01 and
+    Lebesgue discretisation 1e-4 against Euler 1e-5 (and 1e-4), errors
+    against the closed form.  Fine increments at 1e-5 (Nf = 10^5); Magnus sees
+    every tenth node.  Paths: seed 14."""
+    mg = S.mg
+    d = 400
+    coeffs = S.wl.langevin_constant(S.a, S.sigma)
+    dWf = S.increments(14, 10 ** 5)
+    dWc = S.coarse(dWf, 10)
+    u0 = S.u0(d)
+    _, ps = mg.iterated_integrals(dWf, S.T, 1, 2)
+    res = {"d": d}
+    for order in (2, 3):
+        ops = S.operators(coeffs, d, order)
+        uT, fl, ms = S.magnus(ops, dWc, 100, order, u0)
+        res[f"M{order}, 0.01"] = dict(S.err_exact(ops, uT, fl, ps), ms_per_path=ms)
+        log(f"d=400 M{order}: {res[f'M{order}, 0.01']}")
+        del uT
+        ops.close()
+    ops = S.operators(coeffs, d, 2)
+    for dt in (1e-4, 1e-5):
+        u, fl, ms = S.euler(ops, dWf, dt, u0)
+        res[f"E, {dt:g}"] = dict(S.err_exact(ops, u, fl, ps), ms_per_path=ms)
+        log(f"d=400 Euler dt={dt:g}: {res[f'E, {dt:g}']}")
+        del u
+    ops.close()
+    return {"experiment": "constant coefficients at d = 400 (Conclusions)", "paths": S.M,
+            "fine_increments": 10 ** 5, "magnus_increments": 10 ** 4, "seed": 14, "results": [res]}
+
+
+SWEEPS = {"constant": sweep_constant_comparison, "steps": sweep_constant_steps,
+          "variable": sweep_variable, "d400": sweep_d400}
+
+
+def paper_sweep(args):
+    """The paper-parameter experiments; one JSON line per experiment."""
+    S = _Sweep()
+    names = list(SWEEPS) if args.paper_sweep == "all" else [args.paper_sweep]
+    for name in names:
+        out = SWEEPS[name](S)
+        out.update({"a": S.a, "sigma": S.sigma, "domain": [S.lo, S.hi], "kappa": S.kappa,
+                    "T": S.T, "dtype": "f64", "data": "synthetic"})
+        print(json.dumps(out), flush=True)
 
 
 def main():
@@ -472,9 +661,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (torch copy_ kernel) so "
                          "that profiler byte counters can be scaled against a known size")
-    ap.add_argument("--paper-sweep", action="store_true",
-                    help="run the paper's constant-coefficient comparison (d = 100, 200, 300) "
-                         "instead of the benchmark line")
+    ap.add_argument("--paper-sweep", nargs="?", const="constant",
+                    choices=sorted(SWEEPS) + ["all"],
+                    help="run one of the paper-parameter experiments (default: the "
+                         "constant-coefficient comparison for d = 100, 200, 300) instead of the "
+                         "benchmark line")
     args = ap.parse_args()
     if args.paper_sweep:
         return paper_sweep(args)

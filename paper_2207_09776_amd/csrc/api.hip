@@ -99,11 +99,18 @@ mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32
     if (e == hipSuccess)
         e = hipMemcpy(ops->basis_dev, ops->basis_host.data(), bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess && ops->ND > 0) {
-        // x vectors, their statistics, chain vectors and chain statistics
+        // x vectors, their statistics, x-term vectors and statistics, then the
+        // x-term descriptors (int32, at a 16-byte aligned offset)
         std::vector<double> all(ops->xdiag_host);
         all.insert(all.end(), ops->xstat_host.begin(), ops->xstat_host.end());
         all.insert(all.end(), ops->xchain_host.begin(), ops->xchain_host.end());
         all.insert(all.end(), ops->cstat_host.begin(), ops->cstat_host.end());
+        if (all.size() % 2) all.push_back(0.0);
+        ops->xdesc_off = all.size();
+        all.resize(all.size() + (ops->xdesc_host.size() + 1) / 2, 0.0);
+        if (!ops->xdesc_host.empty())
+            std::memcpy(all.data() + ops->xdesc_off, ops->xdesc_host.data(),
+                        ops->xdesc_host.size() * sizeof(int32_t));
         e = hipMalloc((void**)&ops->xdiag_dev, all.size() * sizeof(double));
         if (e == hipSuccess)
             e = hipMemcpy(ops->xdiag_dev, all.data(), all.size() * sizeof(double),

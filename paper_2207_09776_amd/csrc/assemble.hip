@@ -46,9 +46,9 @@ struct AsmArgs {
     int ND, RW;                // x-dependent factors (0: none) and their band radius
     const double* xstat;       // per factor {sum, midpoint, half-width, 0}
     int use24;                 // theta table for 2^-24 instead of 2^-53
-    int NC, NCB;               // chain terms and their coefficients per row (FP64 only)
-    const double* basis_c;     // chain section of the basis [6][nv_pad][NCB]
-    const double* cstat;       // per chain {max|alpha| max|beta|, 0, 0, 0}
+    int NC, NCB;               // x-terms and their coefficients per row (FP64 only)
+    const double* basis_c;     // x-term section of the basis [6][nv_pad][NCB]
+    const double* cstat;       // per x-term X {||X||_1, tr X, 0, 0} (raw differences)
 };
 
 __device__ inline double coeff(const AsmArgs& a, const double* c, int j, int idx) {
@@ -93,12 +93,14 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
     const int wl = 2 * a.RW + 1;
     const int nx = a.nx, nv = a.nv;
 
-    // trace: sum_j (nx * V0[j][0] + tr(Dt^2) * V2[j][0] + sum_t W_t[j][0] * sum_i a_t(i))
+    // trace: sum_j (nx * V0[j][0] + tr(Dt^2) * V2[j][0] + sum_t W_t[j][0] * sum_i a_t(i)
+    //              + sum_k C_k[j][0] * tr X_k)
     const double trDt2 = nx >= 2 ? -(2.0 * nx - 2.0) : 0.0;
     double tr = 0.0;
     for (int j = t; j < nv; j += kThreads) {
         tr += nx * coeff(a, c, j, o0 + a.R0) + (v2 ? trDt2 * coeff(a, c, j, o2 + a.R2) : 0.0);
         for (int f = 0; f < a.ND; ++f) tr += coeff(a, c, j, o3 + f * wl + a.RW) * a.xstat[4 * f];
+        for (int f = 0; f < a.NC; ++f) tr += coeff_c(a, c, j, f * wl + a.RW) * a.cstat[4 * f + 1];
     }
     tr = block_reduce(tr, red, false);
     const double mu = tr / ((double)nx * nv);
@@ -129,13 +131,10 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
             sum += fabs(d0 + a2 * dt2_diag(ip, nx)) + spread;
             if (ip + 1 < nx) sum += fabs(a1);
             if (ip + 2 < nx) sum += fabs(a2);
-            // chain terms C (x) diag(alpha) Dt diag(beta): column ip has entries
-            // alpha_{ip -+ 1} beta_ip in rows ip -+ 1
-            if (b >= -a.RW && b <= a.RW) {
-                const double nb = (ip - 1 >= 0 ? 1.0 : 0.0) + (ip + 1 < nx ? 1.0 : 0.0);
+            // x-terms C (x) X: a column of X sums to at most ||X||_1
+            if (b >= -a.RW && b <= a.RW)
                 for (int f = 0; f < a.NC; ++f)
-                    sum += fabs(coeff_c(a, c, j, f * wl + b + a.RW)) * a.cstat[4 * f] * nb;
-            }
+                    sum += fabs(coeff_c(a, c, j, f * wl + b + a.RW)) * a.cstat[4 * f];
         }
         best = fmax(best, sum);
         if (sum != sum) best = sum;   // keep NaN visible
@@ -188,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void assemble_kernel(AsmArgs a) {
             }
             reinterpret_cast<double*>(rows)[idx] = v * inv_s;
         }
-        // chain section (no trace shift: the chains have no diagonal)
+        // x-term section (the trace shift is taken from the V0 centre only)
         double* crows = reinterpret_cast<double*>(rows) + (size_t)a.nv_pad * a.NBP;
         for (int idx = t; idx < a.nv_pad * a.NCB; idx += kThreads) {
             const int j = idx / a.NCB, e = idx % a.NCB;

@@ -66,8 +66,10 @@ struct CoopArgs {
     int32_t* stats;
     int32_t* flags;
     const double* xdiag;   // x vectors of the x-dependent factors [ND][nx]
-    const double* xchain;  // chain vectors [NC][alpha, beta][nx]
-    int nv_pad;            // table rows before the chain section
+    const double* xchain;  // x-term vectors [nxv][nx]
+    const int4* xdesc;     // x-term descriptors [nxt] {depth, outer, middle, inner}
+    int nxt, nxv;          // x-terms and their vectors (0: none)
+    int nv_pad;            // table rows before the x-term section
     XArea x;
 };
 
@@ -303,12 +305,12 @@ constexpr bool xa_in_lds() {
 }
 
 // LDS: halo | abort word (16 bytes) | x vectors [ND][64*PX] (when in LDS) |
-// chain vectors [NC][2][64*PX]
-template <int PX, int NW, int RH, int ND, class T, int NC = 0>
+// x-term vectors [nxv][64*PX] (their count is known at launch only: the
+// launch adds them)
+template <int PX, int NW, int RH, int ND, class T>
 constexpr size_t coop_lds_bytes() {
     return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + 16 +
-           (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX * sizeof(T) : 0) +
-           (size_t)NC * 2 * 64 * PX * sizeof(T);
+           (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX * sizeof(T) : 0);
 }
 
 // The x vectors at this lane's points (zero beyond nx), in registers or in LDS
@@ -356,7 +358,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
-    constexpr int NCB = NC * (2 * MG_XDIAG_RADIUS + 1);
+    // x-term coefficients per row (NC > 0: the operator has x-terms)
+    const int ncb = NC > 0 ? a.nxt * (2 * MG_XDIAG_RADIUS + 1) : 0;
     constexpr int RW = NW * RJ;
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
@@ -370,15 +373,15 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     // the x vectors of the x-dependent factors at this lane's points
     T* xl = lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T);
     const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(a.xdiag, xl, lane, nx);
-    // chain vectors [NC][alpha, beta][64*PX] in LDS after the x vectors
+    // x-term vectors [nxv][64*PX] in LDS after the x vectors
     T* cvl = xl + (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX : 0);
     if constexpr (NC > 0) {
-        for (int idx = threadIdx.x; idx < NC * 2 * 64 * PX; idx += 64 * NW) {
-            const int kh = idx / (64 * PX), i = idx % (64 * PX);
-            cvl[idx] = i < nx ? (T)a.xchain[(size_t)kh * nx + i] : T(0);
+        for (int idx = threadIdx.x; idx < a.nxv * 64 * PX; idx += 64 * NW) {
+            const int v = idx / (64 * PX), i = idx % (64 * PX);
+            cvl[idx] = i < nx ? (T)a.xchain[(size_t)v * nx + i] : T(0);
         }
     }
-    auto cvec = [&](int k, int h, int q) -> T { return cvl[(k * 2 + h) * 64 * PX + lane * PX + q]; };
+    const XTerms<PX, T> cvec{a.nxt, a.xdesc, cvl, lane};
     __syncthreads();
 
     // one application of the operator to this wave's rows, in place
@@ -420,9 +423,9 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
             pflag |= tv.flag();
             const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
             auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
-            // chain section of the table (after the nv_pad main rows)
-            const T* crows = tv.rows<T>() + (size_t)a.nv_pad * NBP + (size_t)row0 * NCB;
-            auto ccoef = [&](int r, int e) -> T { return crows[r * NCB + e]; };
+            // x-term section of the table (after the nv_pad main rows)
+            const T* crows = tv.rows<T>() + (size_t)a.nv_pad * NBP + (size_t)row0 * ncb;
+            auto ccoef = [&](int r, int e) -> T { return crows[r * ncb + e]; };
             int terms = 0;
             for (int sub = 0; sub < s && !cg.aborted; ++sub) {
                 T d[RJ][PX];
@@ -891,7 +894,7 @@ hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     *nw = NW;
     *rows = NW * RJ;
     *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND, NC>;
-    *lds = coop_lds_bytes<PX, NW, RH, ND, T, NC>();
+    *lds = coop_lds_bytes<PX, NW, RH, ND, T>();
     return hipSuccess;
 }
 
@@ -1014,15 +1017,20 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, co
     const int* R = ops->R;
     const int qmax = ops->qmax;
     if (kind == CoopKind::Expmv && ops->NC > 0) {
-        // chain terms: FP64, four x-factors, two chains, the order-2 band shape,
-        // the FP64 x-factor workgroup shapes
-        if (precision != MG_FP64 || ops->ND != MG_MAX_XDIAG || ops->NC != MG_MAX_XCHAIN ||
+        // x-terms: FP64, four x-factors, the order-2 band shape, the FP64
+        // x-factor workgroup shapes; the x-term vectors add to the LDS
+        if (precision != MG_FP64 || ops->ND != MG_MAX_XDIAG ||
             !(R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1))
             return hipErrorInvalidValue;
         const bool full = ops->grid.nx == 64 * sh.PX;
+        const size_t xv = (size_t)ops->NXV * 64 * sh.PX * sizeof(double);
 #define MG_CHAIN_INFO(PX, RJ, NW, FX)                                                            \
-    return coop_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, MG_MAX_XCHAIN>(      \
-        fn, lds, nw, rows);
+    {                                                                                            \
+        const hipError_t e = coop_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, 1>( \
+            fn, lds, nw, rows);                                                                  \
+        *lds += xv;                                                                              \
+        return e;                                                                                \
+    }
         if (sh.PX == 4) { if (full) { MG_CHAIN_INFO(4, 16, 4, true) } else { MG_CHAIN_INFO(4, 16, 4, false) } }
         if (sh.PX == 8) { if (full) { MG_CHAIN_INFO(8, 8, 4, true) } else { MG_CHAIN_INFO(8, 8, 4, false) } }
 #undef MG_CHAIN_INFO
@@ -1163,6 +1171,9 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
     a.flags = flags;
     a.xdiag = ops->xdiag_dev;
     a.xchain = ops->NC > 0 ? mg_xchain_dev(ops) : nullptr;
+    a.xdesc = ops->NC > 0 ? mg_xdesc_dev(ops) : nullptr;
+    a.nxt = ops->NC;
+    a.nxv = ops->NXV;
     a.nv_pad = ops->nv_pad;
     a.x = xarea_of(xarea, plan);
     const int nfl = plan.ngroups * plan.G;

@@ -123,19 +123,20 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
     const char* __restrict__ tables, size_t tbytes, int K, int nx, int nv,
     const double* __restrict__ u0, int u0_bcast, double* __restrict__ uT, double tol,
     int32_t* __restrict__ stats, int32_t* __restrict__ flags, const double* __restrict__ xdiag,
-    const double* __restrict__ xchain) {
+    const double* __restrict__ xvecs, const int4* __restrict__ xdesc, int nxt, int nxv) {
     using T = double;
     using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     constexpr int NBP = table_stride<R0, R1, R2, QMAX, ND>();
-    constexpr int NCB = NC * (2 * MG_XDIAG_RADIUS + 1);
+    // x-term coefficients per row (NC > 0: the operator has x-terms)
+    const int ncb = NC > 0 ? nxt * (2 * MG_XDIAG_RADIUS + 1) : 0;
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     Halo<PX, RJ, NW, RH, T> halo{lds};
     T* red = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T);   // [2][NW][2] term norms
     T* red2 = red + 2 * NW * 2;                                 // [2][NW] state norms
     int* sflag = reinterpret_cast<int*>(red2 + 2 * NW);
-    // chain vectors [NC][alpha, beta][64*PX] after the flag word (16 bytes)
+    // x-term vectors [nxv][64*PX] after the flag word (16 bytes)
     T* cvl = red2 + 2 * NW + 2;
 
     const int lane = threadIdx.x & 63;
@@ -156,15 +157,15 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
             const int i = lane * PX + q;
             xa[t][q] = (ND > 0 && i < nx) ? (T)xdiag[(size_t)t * nx + i] : T(0);
         }
-    // chain vectors at every lane's points into LDS (zero beyond nx; read
+    // x-term vectors at every lane's points into LDS (zero beyond nx; read
     // after the first barrier of the term loop)
     if constexpr (NC > 0) {
-        for (int idx = threadIdx.x; idx < NC * 2 * 64 * PX; idx += 64 * NW) {
-            const int kh = idx / (64 * PX), i = idx % (64 * PX);
-            cvl[idx] = i < nx ? xchain[(size_t)kh * nx + i] : 0.0;
+        for (int idx = threadIdx.x; idx < nxv * 64 * PX; idx += 64 * NW) {
+            const int v = idx / (64 * PX), i = idx % (64 * PX);
+            cvl[idx] = i < nx ? xvecs[(size_t)v * nx + i] : 0.0;
         }
     }
-    auto cvec = [&](int k, int h, int q) -> T { return cvl[(k * 2 + h) * 64 * PX + lane * PX + q]; };
+    const XTerms<PX, T> cvec{nxt, xdesc, cvl, lane};
 
     T F[RJ][PX];
     {
@@ -201,8 +202,8 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
         const double es = tv.es();
         pflag |= tv.flag();
         const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
-        // chain section: after the NW*RJ main rows (the table's padded rows)
-        const T* crows = tv.rows<T>() + (size_t)NW * RJ * NBP + (size_t)row0 * NCB;
+        // x-term section: after the NW*RJ main rows (the table's padded rows)
+        const T* crows = tv.rows<T>() + (size_t)NW * RJ * NBP + (size_t)row0 * ncb;
         int terms = 0;
         for (int sub = 0; sub < s; ++sub) {
             // the Taylor terms alternate between A and B (no copies between terms)
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_kernel(
                     }
                 };
                 if constexpr (NC > 0) {
-                    auto ccoef = [crows](int r, int e) -> T { return crows[r * NCB + e]; };
+                    auto ccoef = [crows, ncb](int r, int e) -> T { return crows[r * ncb + e]; };
                     apply_rows_any<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, T, NDX, decltype(coef),
                                    decltype(fb), decltype(ft), decltype(emit), NC,
                                    decltype(ccoef), decltype(cvec)>(
@@ -635,20 +636,21 @@ hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64
                      int32_t* stats, int32_t* flags, hipStream_t s) {
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
     // the tables must have the row layout the kernel reads
-    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>() || ops->NC != NC ||
+    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>() || (ops->NC > 0) != (NC > 0) ||
         (NC > 0 && ops->nv_pad != NW * RJ))
         return hipErrorInvalidValue;
     if (precision == MG_FP64) {
-        constexpr size_t lds = resident_lds_bytes<PX, NW, RH, double>() +
-                               (size_t)NC * 2 * 64 * PX * sizeof(double);
+        const size_t lds = resident_lds_bytes<PX, NW, RH, double>() +
+                           (NC > 0 ? (size_t)ops->NXV * 64 * PX * sizeof(double) : 0);
         auto kern = expmv_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND, NC>;
         (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)lds);
         hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, tables, tbytes, K,
                            ops->grid.nx, ops->grid.nv, u0, bc, uT, tol, stats, flags,
-                           ops->xdiag_dev, NC > 0 ? mg_xchain_dev(ops) : nullptr);
+                           ops->xdiag_dev, NC > 0 ? mg_xchain_dev(ops) : nullptr,
+                           NC > 0 ? mg_xdesc_dev(ops) : nullptr, ops->NC, ops->NXV);
     } else if constexpr (NC > 0) {
-        return hipErrorInvalidValue;   // chains: FP64 only
+        return hipErrorInvalidValue;   // x-terms: FP64 only
     } else {
         constexpr size_t lds =
             f32c_stages_rows<PX>()
@@ -701,12 +703,12 @@ hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE,
     if (R[0] == 2 && R[1] == 1 && R[2] == 1 && qmax == 2) return CALL(PX, RJ, NW, 2, 1, 1, 2, FULLX, 0, 0); \
     if (R[0] == 3 && R[1] == 3 && R[2] == 3 && qmax == 2) return CALL(PX, RJ, NW, 3, 3, 3, 2, FULLX, 0, 0); \
     return hipErrorInvalidValue;
-// operators with chain terms (x-dependent noise meeting D^x): four x-factors,
-// two chains, the order-2 band shape (FP64)
+// operators with x-terms (x-dependent noise meeting D^x): four x-factors, any
+// number of x-terms (a run-time loop), the order-2 band shape (FP64)
 #define MG_FOR_SHAPE_CHAINS(PX, RJ, NW, FULLX, CALL)                                           \
-    if (ops->ND == MG_MAX_XDIAG && ops->NC == MG_MAX_XCHAIN && R[0] == 2 && R[1] == 1 &&       \
-        R[2] == 0 && qmax == 1)                                                                \
-        return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG, MG_MAX_XCHAIN);               \
+    if (ops->ND == MG_MAX_XDIAG && ops->NC > 0 && R[0] == 2 && R[1] == 1 && R[2] == 0 &&       \
+        qmax == 1)                                                                             \
+        return CALL(PX, RJ, NW, 2, 1, 0, 1, FULLX, MG_MAX_XDIAG, 1);                           \
     return hipErrorInvalidValue;
 
 #define MG_SHAPE_CASE(SPX, SRJ, SNW, CALL)                                                     \

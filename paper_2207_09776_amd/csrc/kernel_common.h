@@ -189,40 +189,70 @@ __device__ inline void apply_operator(In din, Coef coef, int lane, int nx, T (&o
     }
 }
 
-// Default for the chain-term accessors of the x-factor operators (no chains).
+// Default for the x-term accessors of the x-factor operators (no x-terms).
 struct NoChains {
     template <class... A>
     __device__ double operator()(A...) const { return 0.0; }
 };
 
-// Chain terms C_k (x) diag(alpha_k) Dt diag(beta_k) of row r, added to y:
-// alpha_k * Dt(beta_k * sum_b C_k[r][b] d(r - RC + b)).  `ccoef(r, e)` is the
-// coefficient e of row r in the chain section of the table (NC bands of
-// 2 RC + 1), `cvec(k, h, q)` the chain vector h (0: alpha, 1: beta) of chain k
-// at this lane's point q (zero beyond nx, so the x edge needs no branch).
-template <int PX, int NC, int RC, class T, class Din, class CCoef, class CVec>
-__device__ inline void add_chains(int r, T (&y)[PX], Din din, CCoef ccoef, CVec cvec) {
+// x-terms C_k (x) X_k of row r, added to y.  X_k = diag(x_0) Dt diag(x_1) ...
+// Dt diag(x_d) has depth d <= 2 (Dt without its 1/(2 dx), which the
+// coefficients carry); `xt.desc(k)` is {d, outer, middle, inner} (vector slots
+// of x_0, x_1 and x_d; a depth-0 or depth-1 term has no middle one),
+// `xt.vec(v, q)` vector v at this lane's point q, zero beyond nx, so the next
+// vector cuts every Dt result back to the grid: the truncated matrix product.
+// `ccoef(r, e)` is coefficient e of row r in the x-term section of the table
+// (xt.n bands of 2 RC + 1).  The term count is a run-time value: one loop
+// iteration per term.
+template <int PX, int RC, class T, class Din, class CCoef, class XT>
+__device__ inline void add_xterms(int r, T (&y)[PX], Din din, CCoef ccoef, const XT& xt) {
     constexpr int WL = 2 * RC + 1;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        T c[WL];
-#pragma unroll
-        for (int b = 0; b < WL; ++b) c[b] = ccoef(r, k * WL + b);
+#pragma unroll 1
+    for (int k = 0; k < xt.n; ++k) {
+        const int4 ds = xt.desc(k);
         T w[PX];
+        {
+            const T c0 = ccoef(r, k * WL);
 #pragma unroll
-        for (int q = 0; q < PX; ++q) w[q] = c[0] * din(r - RC, q);
+            for (int q = 0; q < PX; ++q) w[q] = c0 * din(r - RC, q);
+        }
 #pragma unroll
-        for (int b = 1; b < WL; ++b)
+        for (int b = 1; b < WL; ++b) {
+            const T c = ccoef(r, k * WL + b);
 #pragma unroll
-            for (int q = 0; q < PX; ++q) w[q] = fma(c[b], din(r - RC + b, q), w[q]);
+            for (int q = 0; q < PX; ++q) w[q] = fma(c, din(r - RC + b, q), w[q]);
+        }
 #pragma unroll
-        for (int q = 0; q < PX; ++q) w[q] *= cvec(k, 1, q);
-        T e[PX];
-        dt_apply<PX, T>(w, e);
+        for (int q = 0; q < PX; ++q) w[q] *= xt.vec(ds.w, q);
+        if (ds.x >= 1) {
+            T e[PX];
+            dt_apply<PX, T>(w, e);
+            if (ds.x == 2) {
 #pragma unroll
-        for (int q = 0; q < PX; ++q) y[q] = fma(cvec(k, 0, q), e[q], y[q]);
+                for (int q = 0; q < PX; ++q) e[q] *= xt.vec(ds.z, q);
+                dt_apply<PX, T>(e, w);
+            } else {
+#pragma unroll
+                for (int q = 0; q < PX; ++q) w[q] = e[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PX; ++q) y[q] = fma(xt.vec(ds.y, q), w[q], y[q]);
     }
 }
+
+// The x-term accessor of the kernels: descriptors in global memory (read at
+// wave-uniform addresses, so through the scalar cache), vectors
+// [NXV][64*PX] in LDS.
+template <int PX, class T>
+struct XTerms {
+    int n;
+    const int4* __restrict__ descs;
+    const T* vecs;
+    int lane;
+    __device__ int4 desc(int k) const { return descs[k]; }
+    __device__ T vec(int v, int q) const { return vecs[v * 64 * PX + lane * PX + q]; }
+};
 
 // One application of the banded-Kronecker operator to the RJ rows of this
 // wave, in place: d holds the input rows, top/bot the RH halo rows above and
@@ -353,7 +383,7 @@ __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
 #pragma unroll
                 for (int q = 0; q < PX; ++q) y[q] = fma(xa(t, q), z[q], y[q]);
             }
-            if constexpr (NC > 0) add_chains<PX, NC, RW, T>(r, y, din, ccoef, cvec);
+            if constexpr (NC > 0) add_xterms<PX, RW, T>(r, y, din, ccoef, cvec);
             emit(r, y);
         });
 }
@@ -563,7 +593,7 @@ __device__ inline void apply_split_x(const T (&d)[RJ][PX], T (&out)[RJ][PX], T (
 #pragma unroll
                 for (int q = 0; q < PX; ++q) y[q] = fma(xa[t][q], z[q], y[q]);
             }
-            if constexpr (NC > 0) add_chains<PX, NC, RW, T>(r, y, din, ccoef, cvec);
+            if constexpr (NC > 0) add_xterms<PX, RW, T>(r, y, din, ccoef, cvec);
             emit(r, y);
         });
 }

@@ -28,8 +28,9 @@
 constexpr int MG_NBASIS = 6;
 constexpr int MG_HDR = 8;          // table header entries (doubles)
 constexpr int MG_MAX_XDIAG = 4;    // most x-dependent factors the kernels take
-constexpr int MG_XDIAG_RADIUS = 2; // band radius of their v factors (and of the chain factors)
-constexpr int MG_MAX_XCHAIN = 2;   // chains diag(a) D^x diag(b) the kernels take
+constexpr int MG_XDIAG_RADIUS = 2; // band radius of their v factors (and of the x-term factors)
+constexpr int MG_MAX_XTERM = 32;   // x-terms C (x) diag(x_0) D^x ... diag(x_d) (d <= 2)
+constexpr int MG_MAX_XVEC = 16;    // distinct x vectors of the x-terms
 
 struct mg_ops {
     mg_grid grid;
@@ -40,17 +41,23 @@ struct mg_ops {
     int nactive;                   // basis matrices used by `order` (2, 4 or 6)
     int nv_pad;                    // table rows: nv rounded up to the kernel's rows (zeros)
     int ND = 0, RW = 0;            // x-dependent factors and their band radius
-    int NC = 0, NCB = 0;           // chain terms C (x) diag(a) D^x diag(b) (0 or
-                                   // MG_MAX_XCHAIN) and their coefficients per row
-                                   // (NC bands of radius MG_XDIAG_RADIUS)
+    int NC = 0, NCB = 0;           // x-terms C (x) X with X = diag(x_0) D^x diag(x_1)
+                                   // ... D^x diag(x_d), d <= 2, that the diagonal
+                                   // x-factors cannot hold, and their coefficients
+                                   // per row (NC bands of radius MG_XDIAG_RADIUS)
+    int NXV = 0;                   // distinct x vectors of the x-terms
     // basis tables, host copy and device copy: [MG_NBASIS][nv_pad][NBP], then
-    // the chain section [MG_NBASIS][nv_pad][NCB]
+    // the x-term section [MG_NBASIS][nv_pad][NCB]
     std::vector<double> basis_host;
     double* basis_dev = nullptr;
     // x vectors a_t [ND][nx] and per factor {sum, midpoint, half-width, 0};
-    // chain vectors [NC][alpha, beta][nx] and per chain {max|alpha| max|beta|, 0, 0, 0}
+    // x-term vectors [NXV][nx] (vector 0 is the unit vector) and per x-term
+    // {||X||_1, tr X, 0, 0} with D^x taken without its 1/(2 dx);
+    // x-term descriptors [NC][4] = {d, slot of x_0, slot of x_1, slot of x_d}
     std::vector<double> xdiag_host, xstat_host, xchain_host, cstat_host;
-    double* xdiag_dev = nullptr;   // xdiag, xstat, xchain, cstat in one allocation
+    std::vector<int32_t> xdesc_host;
+    double* xdiag_dev = nullptr;   // xdiag, xstat, xchain, cstat, xdesc in one allocation
+    size_t xdesc_off = 0;          // offset of xdesc in it (doubles, even)
     int device = 0;
     // register-resident kernel shape (PX, RJ, NW) recorded by the autotuner
     // per precision (FP64, FP32C); zeros: the default shape
@@ -63,7 +70,7 @@ struct mg_ops {
 //                   [f64 ||Y - mu I||_1] [int32 flag, pad] [2 x f64 reserved]
 //   then nv_pad rows of NBP coefficients of (Y - mu I)/s, FP64 (MG_FP64) or
 //   FP32 rounded from FP64 with each band's rounding residual in its centre
-//   entry (MG_FP32C), then nv_pad rows of the NCB chain coefficients (FP64
+//   entry (MG_FP32C), then nv_pad rows of the NCB x-term coefficients (FP64
 //   only); records are 64-byte aligned.
 inline size_t mg_table_bytes(const mg_ops* ops, int precision) {
     const size_t elem = precision == MG_FP32C ? 4 : 8;
@@ -71,8 +78,9 @@ inline size_t mg_table_bytes(const mg_ops* ops, int precision) {
     return (b + 63) & ~(size_t)63;
 }
 
-// device copies of the per-factor statistics and of the chain vectors, which
-// follow the x vectors in the xdiag_dev allocation
+// device copies of the per-factor statistics and of the x-term vectors,
+// statistics and descriptors, which follow the x vectors in the xdiag_dev
+// allocation
 inline const double* mg_xstat_dev(const mg_ops* ops) {
     return ops->xdiag_dev + ops->xdiag_host.size();
 }
@@ -81,6 +89,9 @@ inline const double* mg_xchain_dev(const mg_ops* ops) {
 }
 inline const double* mg_cstat_dev(const mg_ops* ops) {
     return mg_xchain_dev(ops) + ops->xchain_host.size();
+}
+inline const int4* mg_xdesc_dev(const mg_ops* ops) {
+    return reinterpret_cast<const int4*>(ops->xdiag_dev + ops->xdesc_off);
 }
 
 // error state (thread local, defined in api.hip)

@@ -16,14 +16,16 @@
 // Sigma, Sigma^v in A) may also depend on x.  Such a coefficient grid z(x, v)
 // is written exactly (to rounding) as a short sum sum_t b_t(v) a_t(x) by a
 // cross decomposition with complete pivoting, so diag(vec Z) = sum_t
-// diag(b_t) (x) diag(a_t): the operators gain terms W (x) diag(a) next to the
-// V_q (x) D^q terms.  Where D^x meets such a factor once in a product (the
-// commutators of eq. (MagnusFormulas) with x-dependent noise through d/dv,
-// as in eq. (coeffsLangevinVar)), the x part is a chain
-// diag(alpha) D^x diag(beta) (one of alpha, beta may be the unit vector):
-// the operators gain terms C (x) diag(alpha) D^x diag(beta).  Products that
-// would need a second D^x on a chain, or a chain times a chain, are reported
-// as unsupported.
+// diag(b_t) (x) diag(a_t).  Every operator is then a sum of terms V (x) X
+// with X a word diag(x_0) D^x diag(x_1) ... D^x diag(x_d) in the x vectors
+// (the unit vector included) and D^x; a product of two terms is the product
+// of the V factors times the concatenated word, whose two middle vectors
+// merge into their pointwise product: again exact, as products of the
+// truncated matrices.  Words of depth up to 2 occur at order 3 of
+// eq. (coeffsLangevinVar) (x-dependent noise through d/dv meets -v d/dx twice
+// in [[B,A],B]); deeper words are reported as unsupported.  The kernels take
+// words with unit vectors only (powers of D^x) as the V_q tables, depth-0
+// words as diagonal x-factors, and the others as x-terms.
 
 #include <algorithm>
 #include <cmath>
@@ -114,34 +116,49 @@ struct XReg {
     }
 };
 
-// sum_{q=0..2} V[q] (x) (D^x)^q + sum_k W[k] (x) diag(xreg.vecs[id[k]])
-//   + sum_k C[k] (x) diag(a_k) D^x diag(b_k)   (a_k = vecs[ca[k]], b_k =
-//   vecs[cb[k]], index -1: the unit vector)
-struct KOp {
-    Band V[3];
-    std::vector<Band> W;
-    std::vector<int> id;
-    std::vector<Band> C;
-    std::vector<int> ca, cb;
-    explicit KOp(int nv) { for (auto& b : V) b = band_zero(nv); }
-    void add_w(int xid, const Band& B) {
-        for (size_t k = 0; k < id.size(); ++k)
-            if (id[k] == xid) {
-                W[k] = band_axpby(1.0, W[k], 1.0, B);
-                return;
-            }
-        id.push_back(xid);
-        W.push_back(B);
+// An x word diag(x_0) Dt diag(x_1) ... Dt diag(x_d), d <= 2, with Dt =
+// tridiag(-1, 0, 1) (D^x without its 1/(2 dx)); x_h is a registry id, -1 for
+// the unit vector.
+struct XWord {
+    int d = 0;
+    int id[3] = {-1, -1, -1};
+    bool unit() const {
+        for (int h = 0; h <= d; ++h)
+            if (id[h] >= 0) return false;
+        return true;
     }
-    void add_c(int ia, int ib, const Band& B) {
-        for (size_t k = 0; k < ca.size(); ++k)
-            if (ca[k] == ia && cb[k] == ib) {
-                C[k] = band_axpby(1.0, C[k], 1.0, B);
+    bool operator==(const XWord& o) const {
+        if (d != o.d) return false;
+        for (int h = 0; h <= d; ++h)
+            if (id[h] != o.id[h]) return false;
+        return true;
+    }
+};
+
+// sum_k V[k] (x) X_k over distinct words X_k
+struct KOp {
+    int nv;
+    std::vector<XWord> w;
+    std::vector<Band> V;
+    explicit KOp(int nv_) : nv(nv_) {}
+    void add(const XWord& x, const Band& B) {
+        for (size_t k = 0; k < w.size(); ++k)
+            if (w[k] == x) {
+                V[k] = band_axpby(1.0, V[k], 1.0, B);
                 return;
             }
-        ca.push_back(ia);
-        cb.push_back(ib);
-        C.push_back(B);
+        w.push_back(x);
+        V.push_back(B);
+    }
+    void add_q(int q, const Band& B) {   // B (x) Dt^q
+        XWord x;
+        x.d = q;
+        add(x, B);
+    }
+    void add_w(int xid, const Band& B) {   // B (x) diag(x vector xid)
+        XWord x;
+        x.id[0] = xid;
+        add(x, B);
     }
 };
 
@@ -156,107 +173,59 @@ int xmul(XReg& xr, int ia, int ib) {
     return xr.find_or_add(ab);
 }
 
-// Product of two factored operators; false (with a reason) when a power of
-// D^x meets a non-constant diagonal x-factor, which this form cannot hold.
+// Product of two factored operators; false (with a reason) when a word would
+// exceed depth 2.
 bool kop_mul(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
-    int nv = X.V[0].n;
-    KOp Z(nv);
-    for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) {
-            if (band_is_zero(X.V[p]) || band_is_zero(Y.V[q])) continue;
-            Band P = band_mul(X.V[p], Y.V[q]);
+    KOp Z(X.nv);
+    for (size_t s = 0; s < X.w.size(); ++s)
+        for (size_t t = 0; t < Y.w.size(); ++t) {
+            if (band_is_zero(X.V[s]) || band_is_zero(Y.V[t])) continue;
+            Band P = band_mul(X.V[s], Y.V[t]);
             if (band_is_zero(P)) continue;
-            if (p + q > 2) { why = "x-derivative power above 2 in the Magnus basis"; return false; }
-            Z.V[p + q] = band_axpby(1.0, Z.V[p + q], 1.0, P);
+            const XWord& a = X.w[s];
+            const XWord& b = Y.w[t];
+            if (a.d + b.d > 2) {
+                why = a.unit() && b.unit()
+                          ? "x-derivative power above 2 in the Magnus basis"
+                          : "an x derivative meets x-dependent coefficients more than twice in a "
+                            "product of the Magnus basis";
+                return false;
+            }
+            XWord c;
+            c.d = a.d + b.d;
+            for (int h = 0; h < a.d; ++h) c.id[h] = a.id[h];
+            c.id[a.d] = xmul(xr, a.id[a.d], b.id[0]);
+            for (int h = 1; h <= b.d; ++h) c.id[a.d + h] = b.id[h];
+            Z.add(c, P);
         }
-    const char* deep = "an x derivative meets an x-dependent coefficient more than once in the "
-                       "Magnus basis (order 3 with x-dependent noise)";
-    // (V (x) D^p)(W (x) diag(a)): diag for p = 0, the chain D diag(a) for p = 1
-    for (size_t k = 0; k < Y.W.size(); ++k)
-        for (int p = 0; p < 3; ++p) {
-            if (band_is_zero(X.V[p]) || band_is_zero(Y.W[k])) continue;
-            Band P = band_mul(X.V[p], Y.W[k]);
-            if (band_is_zero(P)) continue;
-            if (p > 1) { why = deep; return false; }
-            if (p == 0) Z.add_w(Y.id[k], P);
-            else Z.add_c(-1, Y.id[k], P);
-        }
-    // (V (x) D^p) chain: only p = 0
-    for (size_t k = 0; k < Y.C.size(); ++k)
-        for (int p = 0; p < 3; ++p) {
-            if (band_is_zero(X.V[p]) || band_is_zero(Y.C[k])) continue;
-            Band P = band_mul(X.V[p], Y.C[k]);
-            if (band_is_zero(P)) continue;
-            if (p > 0) { why = deep; return false; }
-            Z.add_c(Y.ca[k], Y.cb[k], P);
-        }
-    // chain (V (x) D^q): only q = 0; chain (W (x) diag(b)) = chain with beta b
-    for (size_t k = 0; k < X.C.size(); ++k) {
-        for (int q = 0; q < 3; ++q) {
-            if (band_is_zero(X.C[k]) || band_is_zero(Y.V[q])) continue;
-            Band P = band_mul(X.C[k], Y.V[q]);
-            if (band_is_zero(P)) continue;
-            if (q > 0) { why = deep; return false; }
-            Z.add_c(X.ca[k], X.cb[k], P);
-        }
-        for (size_t m = 0; m < Y.W.size(); ++m) {
-            if (band_is_zero(X.C[k]) || band_is_zero(Y.W[m])) continue;
-            Band P = band_mul(X.C[k], Y.W[m]);
-            if (band_is_zero(P)) continue;
-            Z.add_c(X.ca[k], xmul(xr, X.cb[k], Y.id[m]), P);
-        }
-        for (size_t m = 0; m < Y.C.size(); ++m) {
-            if (band_is_zero(X.C[k]) || band_is_zero(Y.C[m])) continue;
-            if (band_is_zero(band_mul(X.C[k], Y.C[m]))) continue;
-            why = deep;
-            return false;
-        }
-    }
-    for (size_t k = 0; k < X.W.size(); ++k) {
-        // (W (x) diag(a))(V (x) D^q): diag for q = 0, the chain diag(a) D for q = 1
-        for (int q = 0; q < 3; ++q) {
-            if (band_is_zero(X.W[k]) || band_is_zero(Y.V[q])) continue;
-            Band P = band_mul(X.W[k], Y.V[q]);
-            if (band_is_zero(P)) continue;
-            if (q > 1) { why = deep; return false; }
-            if (q == 0) Z.add_w(X.id[k], P);
-            else Z.add_c(X.id[k], -1, P);
-        }
-        // (W (x) diag(a)) chain = chain with alpha a * alpha
-        for (size_t m = 0; m < Y.C.size(); ++m) {
-            if (band_is_zero(X.W[k]) || band_is_zero(Y.C[m])) continue;
-            Band P = band_mul(X.W[k], Y.C[m]);
-            if (band_is_zero(P)) continue;
-            Z.add_c(xmul(xr, X.id[k], Y.ca[m]), Y.cb[m], P);
-        }
-        for (size_t m = 0; m < Y.W.size(); ++m) {
-            if (band_is_zero(X.W[k]) || band_is_zero(Y.W[m])) continue;
-            Band P = band_mul(X.W[k], Y.W[m]);
-            if (band_is_zero(P)) continue;
-            const std::vector<double>& a = xr.vecs[X.id[k]];
-            const std::vector<double>& b = xr.vecs[Y.id[m]];
-            std::vector<double> ab(a.size());
-            for (size_t i = 0; i < a.size(); ++i) ab[i] = a[i] * b[i];
-            Z.add_w(xr.find_or_add(ab), P);
-        }
-    }
     out = Z;
     return true;
 }
 
 bool kop_comm(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
-    const int nv = X.V[0].n;
-    KOp XY(nv), YX(nv);
+    KOp XY(X.nv), YX(X.nv);
     if (!kop_mul(X, Y, xr, XY, why) || !kop_mul(Y, X, xr, YX, why)) return false;
-    KOp Z(nv);
-    for (int q = 0; q < 3; ++q) Z.V[q] = band_axpby(1.0, XY.V[q], -1.0, YX.V[q]);
-    for (size_t k = 0; k < XY.W.size(); ++k) Z.add_w(XY.id[k], XY.W[k]);
-    for (size_t k = 0; k < YX.W.size(); ++k) Z.add_w(YX.id[k], band_axpby(-1.0, YX.W[k], 0.0, YX.W[k]));
-    for (size_t k = 0; k < XY.C.size(); ++k) Z.add_c(XY.ca[k], XY.cb[k], XY.C[k]);
-    for (size_t k = 0; k < YX.C.size(); ++k)
-        Z.add_c(YX.ca[k], YX.cb[k], band_axpby(-1.0, YX.C[k], 0.0, YX.C[k]));
+    KOp Z(X.nv);
+    for (size_t k = 0; k < XY.w.size(); ++k) Z.add(XY.w[k], XY.V[k]);
+    for (size_t k = 0; k < YX.w.size(); ++k) Z.add(YX.w[k], band_axpby(-1.0, YX.V[k], 0.0, YX.V[k]));
     out = Z;
     return true;
+}
+
+// The x word as an nx x nx band matrix (Dt without its 1/(2 dx)), for the
+// 1-norm and the trace of an x-term.
+Band word_matrix(const XWord& x, const XReg& xr, int nx) {
+    auto vec = [&](int id) {
+        return id < 0 ? std::vector<double>((size_t)nx, 1.0) : xr.vecs[id];
+    };
+    Band Dt(nx, 1);
+    for (int i = 0; i < nx; ++i) {
+        if (i > 0) Dt.set(i, i - 1, -1.0);
+        if (i + 1 < nx) Dt.set(i, i + 1, 1.0);
+    }
+    Band M = band_diag(vec(x.id[0]));
+    for (int h = 1; h <= x.d; ++h) M = band_mul(band_mul(M, Dt), band_diag(vec(x.id[h])));
+    return M;
 }
 
 // Exact low-rank form of a coefficient grid z[j][i] (v row j, x column i):
@@ -368,15 +337,16 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
 
     // B = V_0 (x) I + V_1 (x) D^x + sum W (x) diag(a)
     KOp B(nv), A(nv);
-    B.V[0] = band_axpby(1.0, band_diag(c[H]), 1.0, band_mul(band_diag(c[FV]), Dv));
-    B.V[0] = band_axpby(1.0, B.V[0], 0.5, band_mul(band_diag(c[GVV]), Dvv));
-    B.V[1] = band_axpby(1.0, band_diag(c[FX]), 1.0, band_mul(band_diag(c[GXV]), Dv));
+    Band b0 = band_axpby(1.0, band_diag(c[H]), 1.0, band_mul(band_diag(c[FV]), Dv));
+    b0 = band_axpby(1.0, b0, 0.5, band_mul(band_diag(c[GVV]), Dvv));
+    B.add_q(0, b0);
+    B.add_q(1, band_axpby(1.0, band_diag(c[FX]), 1.0, band_mul(band_diag(c[GXV]), Dv)));
     for (size_t r = 0; r < xb[H].size(); ++r) B.add_w(xid[H][r], band_diag(xb[H][r]));
     for (size_t r = 0; r < xb[FV].size(); ++r) B.add_w(xid[FV][r], band_mul(band_diag(xb[FV][r]), Dv));
     for (size_t r = 0; r < xb[GVV].size(); ++r)
         B.add_w(xid[GVV][r], band_axpby(0.5, band_mul(band_diag(xb[GVV][r]), Dvv), 0.0, Dvv));
     // A = V_0 (x) I + sum W (x) diag(a)
-    A.V[0] = band_axpby(1.0, band_diag(c[SIG]), 1.0, band_mul(band_diag(c[SV]), Dv));
+    A.add_q(0, band_axpby(1.0, band_diag(c[SIG]), 1.0, band_mul(band_diag(c[SV]), Dv)));
     for (size_t r = 0; r < xb[SIG].size(); ++r) A.add_w(xid[SIG][r], band_diag(xb[SIG][r]));
     for (size_t r = 0; r < xb[SV].size(); ++r) A.add_w(xid[SV][r], band_mul(band_diag(xb[SV][r]), Dv));
 
@@ -389,15 +359,37 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     if (nact > 4) ok = ok && kop_comm(M[3], A, xr, M[4], why) && kop_comm(M[3], B, xr, M[5], why);
     if (!ok) return mg_fail(MG_EUNSUPPORTED, why);
 
+    // The three kinds of terms: words with unit vectors only (powers of D^x,
+    // the V_q tables), depth-0 words (diagonal x-factors W (x) diag(a)) and
+    // the other words (x-terms C (x) X).
+    struct Split {
+        Band V[3];
+        std::vector<int> wid;
+        std::vector<Band> W;
+        std::vector<XWord> xw;
+        std::vector<Band> X;
+    };
+    std::vector<Split> S(MG_NBASIS);
+    for (int l = 0; l < MG_NBASIS; ++l) {
+        for (auto& b : S[l].V) b = band_zero(nv);
+        for (size_t k = 0; k < M[l].w.size(); ++k) {
+            const XWord& x = M[l].w[k];
+            if (x.unit()) S[l].V[x.d] = band_axpby(1.0, S[l].V[x.d], 1.0, M[l].V[k]);
+            else if (x.d == 0) { S[l].wid.push_back(x.id[0]); S[l].W.push_back(M[l].V[k]); }
+            else { S[l].xw.push_back(x); S[l].X.push_back(M[l].V[k]); }
+        }
+    }
+
     // Band radii actually used, after dropping cancellation residues.  A
-    // factor V_q multiplies (D^x)^q, whose norm is about (1/dx)^q, and a factor
-    // W multiplies diag(a), whose norm is max|a|, so entries are compared with
-    // the whole matrix through these weights: entries below 1e-14 of the
+    // factor V_q multiplies (D^x)^q, whose norm is about (1/dx)^q, a factor W
+    // multiplies diag(a), whose norm is max|a|, and an x-term factor multiplies
+    // a word of norm about prod_h max|x_h| (1/dx)^d, so entries are compared
+    // with the whole matrix through these weights: entries below 1e-14 of the
     // largest weighted entry of the same basis matrix are zero in exact
     // arithmetic and stem from rounding in the products (a factor can consist
     // of residues only, e.g. the D^x part of [[B,A],B] for the
     // constant-coefficient operator).
-    int R[3] = {0, 0, 0}, RW = 0;
+    int R[3] = {0, 0, 0}, RW = 0, RC = 0;
     const double wq[3] = {1.0, 1.0 / dx, 1.0 / (dx * dx)};
     std::vector<double> wa(xr.vecs.size());
     for (size_t k = 0; k < xr.vecs.size(); ++k) {
@@ -405,79 +397,105 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         for (double v : xr.vecs[k]) m = std::max(m, std::fabs(v));
         wa[k] = m;
     }
-    std::vector<int> used(xr.vecs.size(), 0);
-    // chain terms: weight max|alpha| max|beta| / dx, and the distinct chains
-    // the active matrices use
     auto xmax = [&](int id) { return id < 0 ? 1.0 : wa[id]; };
-    std::vector<std::pair<int, int>> chains;
-    auto chain_slot = [&](int ia, int ib) {
-        for (size_t c = 0; c < chains.size(); ++c)
-            if (chains[c].first == ia && chains[c].second == ib) return (int)c;
-        chains.push_back({ia, ib});
-        return (int)chains.size() - 1;
+    auto wword = [&](const XWord& x) {
+        double w = 1.0;
+        for (int h = 0; h <= x.d; ++h) w *= xmax(x.id[h]);
+        return w * wq[x.d];
     };
-    int RC = 0;
+    std::vector<int> used(xr.vecs.size(), 0);
+    std::vector<XWord> xterms;   // distinct x-terms of the active matrices
+    auto xterm_slot = [&](const XWord& x) {
+        for (size_t k = 0; k < xterms.size(); ++k)
+            if (xterms[k] == x) return (int)k;
+        return -1;
+    };
+    auto radius = [&](const Band& V) {
+        int r = 0;
+        for (int i = 0; i < nv; ++i)
+            for (int o = -V.r; o <= V.r; ++o)
+                if (V.get(i, i + o) != 0.0) r = std::max(r, std::abs(o));
+        return r;
+    };
     for (int l = 0; l < MG_NBASIS; ++l) {
+        Split& T = S[l];
         double mx = 0.0;
         for (int q = 0; q < 3; ++q)
-            for (double v : M[l].V[q].a) mx = std::max(mx, std::fabs(v) * wq[q]);
-        for (size_t k = 0; k < M[l].W.size(); ++k)
-            for (double v : M[l].W[k].a) mx = std::max(mx, std::fabs(v) * wa[M[l].id[k]]);
-        for (size_t k = 0; k < M[l].C.size(); ++k) {
-            const double wc = xmax(M[l].ca[k]) * xmax(M[l].cb[k]) / dx;
-            for (double v : M[l].C[k].a) mx = std::max(mx, std::fabs(v) * wc);
-        }
-        for (size_t k = 0; k < M[l].C.size(); ++k) {
-            Band& C = M[l].C[k];
-            const double wc = xmax(M[l].ca[k]) * xmax(M[l].cb[k]) / dx;
-            for (double& v : C.a)
-                if (std::fabs(v) * wc <= 1e-14 * mx) v = 0.0;
-            if (l >= nact || band_is_zero(C)) continue;
-            for (int i = 0; i < nv; ++i)
-                for (int o = -C.r; o <= C.r; ++o)
-                    if (C.get(i, i + o) != 0.0) RC = std::max(RC, std::abs(o));
-            chain_slot(M[l].ca[k], M[l].cb[k]);
-        }
+            for (double v : T.V[q].a) mx = std::max(mx, std::fabs(v) * wq[q]);
+        for (size_t k = 0; k < T.W.size(); ++k)
+            for (double v : T.W[k].a) mx = std::max(mx, std::fabs(v) * wa[T.wid[k]]);
+        for (size_t k = 0; k < T.X.size(); ++k)
+            for (double v : T.X[k].a) mx = std::max(mx, std::fabs(v) * wword(T.xw[k]));
         for (int q = 0; q < 3; ++q) {
-            Band& V = M[l].V[q];
-            for (double& v : V.a)
+            for (double& v : T.V[q].a)
                 if (std::fabs(v) * wq[q] <= 1e-14 * mx) v = 0.0;
-            if (l >= nact) continue;
-            for (int i = 0; i < nv; ++i)
-                for (int o = -V.r; o <= V.r; ++o)
-                    if (V.get(i, i + o) != 0.0) R[q] = std::max(R[q], std::abs(o));
+            if (l < nact) R[q] = std::max(R[q], radius(T.V[q]));
         }
-        for (size_t k = 0; k < M[l].W.size(); ++k) {
-            Band& W = M[l].W[k];
-            for (double& v : W.a)
-                if (std::fabs(v) * wa[M[l].id[k]] <= 1e-14 * mx) v = 0.0;
-            if (l >= nact) continue;
-            for (int i = 0; i < nv; ++i)
-                for (int o = -W.r; o <= W.r; ++o)
-                    if (W.get(i, i + o) != 0.0) {
-                        RW = std::max(RW, std::abs(o));
-                        used[M[l].id[k]] = 1;
-                    }
+        for (size_t k = 0; k < T.W.size(); ++k) {
+            for (double& v : T.W[k].a)
+                if (std::fabs(v) * wa[T.wid[k]] <= 1e-14 * mx) v = 0.0;
+            if (l >= nact || band_is_zero(T.W[k])) continue;
+            RW = std::max(RW, radius(T.W[k]));
+            used[T.wid[k]] = 1;
+        }
+        for (size_t k = 0; k < T.X.size(); ++k) {
+            const double ww = wword(T.xw[k]);
+            for (double& v : T.X[k].a)
+                if (std::fabs(v) * ww <= 1e-14 * mx) v = 0.0;
+            if (l >= nact || band_is_zero(T.X[k])) continue;
+            RC = std::max(RC, radius(T.X[k]));
+            if (xterm_slot(T.xw[k]) < 0) xterms.push_back(T.xw[k]);
         }
     }
-    // diagonal x-factors in use, numbered 0 .. nd-1 in registry order
+    // diagonal x-factors in use, numbered in registry order; with x-terms
+    // the first MG_MAX_XDIAG keep their own slots (those of B and A, which the
+    // Euler kernels read, come first: the coefficients are registered before
+    // any product) and the others become depth-0 x-terms
     std::vector<int> slot(xr.vecs.size(), -1);
     int nd = 0;
-    for (size_t k = 0; k < xr.vecs.size(); ++k)
-        if (used[k]) slot[k] = nd++;
-    if (nd > MG_MAX_XDIAG)
+    std::vector<int> overflow;
+    for (size_t k = 0; k < xr.vecs.size(); ++k) {
+        if (!used[k]) continue;
+        if (nd < MG_MAX_XDIAG) slot[k] = nd++;
+        else overflow.push_back((int)k);
+    }
+    if (!overflow.empty() && xterms.empty())
         return mg_fail(MG_EUNSUPPORTED, "more than 4 x-dependent factors in the Magnus basis");
+    for (int id : overflow)
+        for (int l = 0; l < 2; ++l)
+            for (int w : S[l].wid)
+                if (w == id)
+                    return mg_fail(MG_EUNSUPPORTED,
+                                   "more than 4 x-dependent factors in B and A together");
+    for (int id : overflow) {
+        XWord x;
+        x.id[0] = id;
+        xterms.push_back(x);
+        RC = std::max(RC, RW);
+    }
     if (RW > MG_XDIAG_RADIUS)
         return mg_fail(MG_EUNSUPPORTED, "band radius of an x-dependent factor above 2");
-    if ((int)chains.size() > MG_MAX_XCHAIN)
-        return mg_fail(MG_EUNSUPPORTED, "more than 2 chains diag(a) D^x diag(b) in the Magnus basis");
+    if ((int)xterms.size() > MG_MAX_XTERM)
+        return mg_fail(MG_EUNSUPPORTED, "more than 32 x-terms in the Magnus basis");
     if (RC > MG_XDIAG_RADIUS)
-        return mg_fail(MG_EUNSUPPORTED, "band radius of a chain factor above 2");
+        return mg_fail(MG_EUNSUPPORTED, "band radius of an x-term factor above 2");
+    // x-term vectors: slot 0 the unit vector, then every other vector the
+    // words use, in registry order
+    std::vector<int> vslot(xr.vecs.size(), -1);
+    int nxv = xterms.empty() ? 0 : 1;
+    for (size_t k = 0; k < xr.vecs.size(); ++k) {
+        bool in = false;
+        for (const XWord& x : xterms)
+            for (int h = 0; h <= x.d; ++h) in = in || x.id[h] == (int)k;
+        if (in) vslot[k] = nxv++;
+    }
+    if (nxv > MG_MAX_XVEC)
+        return mg_fail(MG_EUNSUPPORTED, "more than 16 distinct x vectors in the x-terms");
     // highest power of D^x with a non-zero factor among the active matrices
     int qmax = 0;
     for (int l = 0; l < nact; ++l)
         for (int q = 1; q < 3; ++q)
-            for (double v : M[l].V[q].a)
+            for (double v : S[l].V[q].a)
                 if (v != 0.0) qmax = std::max(qmax, q);
     // Round the radii up to one of the band shapes the kernels are built for;
     // the padding entries are zeros.
@@ -488,8 +506,8 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             qmax <= kShapes[k][3])
             shape = k;
     if (shape < 0) return mg_fail(MG_EUNSUPPORTED, "Magnus basis band radius above 3");
-    if (!chains.empty()) shape = std::max(shape, 1);   // built for the order-2 band shape
-    if ((nd > 0 || !chains.empty()) && shape > 1)
+    if (!xterms.empty()) shape = std::max(shape, 1);   // built for the order-2 band shape
+    if ((nd > 0 || !xterms.empty()) && shape > 1)
         return mg_fail(MG_EUNSUPPORTED,
                        "x-dependent coefficients are built for band shapes up to (2,1,0) in this build");
     for (int q = 0; q < 3; ++q) R[q] = kShapes[shape][q];
@@ -501,8 +519,9 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     for (int q = 0; q < 3; ++q) ops->R[q] = R[q];
     // x-dependent factors: the kernels are built for 3 and for 4 factors
     // (unused ones are zero; the variable-coefficient workloads use 3), and
-    // with chains for 4 factors and 2 chains
-    ops->NC = chains.empty() ? 0 : MG_MAX_XCHAIN;
+    // with x-terms for 4 factors
+    ops->NC = (int)xterms.size();
+    ops->NXV = nxv;
     ops->ND = nd > 0 || ops->NC > 0 ? (nd <= 3 && ops->NC == 0 ? 3 : MG_MAX_XDIAG) : 0;
     ops->RW = ops->ND > 0 ? MG_XDIAG_RADIUS : 0;
     // V2 (the Dt^2 factor) has entries in the row only where Dt^2 occurs
@@ -527,25 +546,41 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         st[1] = 0.5 * (hi + lo);     // midpoint and half-width of the values,
         st[2] = 0.5 * (hi - lo);     // for the 1-norm bound
     }
-    // chain vectors alpha_c, beta_c [NC][2][nx] and per chain {max|alpha| max|beta|, 0, 0, 0}
-    ops->xchain_host.assign((size_t)ops->NC * 2 * nx, 0.0);
+    // x-term vectors [NXV][nx], descriptors {d, outer, middle, inner} and per
+    // x-term {||X||_1, tr X, 0, 0}
+    ops->xchain_host.assign((size_t)nxv * nx, 0.0);
+    for (int i = 0; i < nx && nxv > 0; ++i) ops->xchain_host[i] = 1.0;
+    for (size_t k = 0; k < xr.vecs.size(); ++k)
+        if (vslot[k] >= 0)
+            for (int i = 0; i < nx; ++i) ops->xchain_host[(size_t)vslot[k] * nx + i] = xr.vecs[k][i];
+    ops->xdesc_host.assign((size_t)ops->NC * 4, 0);
     ops->cstat_host.assign((size_t)ops->NC * 4, 0.0);
-    for (size_t c = 0; c < chains.size(); ++c) {
-        const int ids[2] = {chains[c].first, chains[c].second};
-        double mx[2] = {0.0, 0.0};
-        for (int h = 0; h < 2; ++h)
-            for (int i = 0; i < nx; ++i) {
-                const double v = ids[h] < 0 ? 1.0 : xr.vecs[ids[h]][i];
-                ops->xchain_host[(c * 2 + h) * nx + i] = v;
-                mx[h] = std::max(mx[h], std::fabs(v));
-            }
-        ops->cstat_host[c * 4] = mx[0] * mx[1];
+    auto vs = [&](int id) { return id < 0 ? 0 : vslot[id]; };
+    for (int k = 0; k < ops->NC; ++k) {
+        const XWord& x = xterms[k];
+        int32_t* d = ops->xdesc_host.data() + (size_t)k * 4;
+        d[0] = x.d;
+        d[1] = vs(x.id[0]);
+        d[2] = x.d == 2 ? vs(x.id[1]) : 0;
+        d[3] = vs(x.id[x.d]);
+        if (x.d == 0) d[3] = 0;   // the unit vector: the outer vector is the factor
+        const Band X = word_matrix(x, xr, nx);
+        double n1 = 0.0, tr = 0.0;
+        for (int j = 0; j < nx; ++j) {
+            double col = 0.0;
+            for (int i = std::max(0, j - X.r); i <= std::min(nx - 1, j + X.r); ++i)
+                col += std::fabs(X.get(i, j));
+            n1 = std::max(n1, col);
+            tr += X.get(j, j);
+        }
+        ops->cstat_host[(size_t)k * 4] = n1;
+        ops->cstat_host[(size_t)k * 4 + 1] = tr;
     }
     // table rows are padded to the rows the kernel shape covers
     int rows = resident_rows(nx, nv);
     if (rows == 0) rows = coop_table_rows(nx, nv);
     ops->nv_pad = std::max(nv, rows);
-    // main rows [6][nv_pad][NBP], then the chain section [6][nv_pad][NCB]
+    // main rows [6][nv_pad][NBP], then the x-term section [6][nv_pad][NCB]
     ops->NCB = ops->NC * (2 * MG_XDIAG_RADIUS + 1);
     ops->basis_host.assign((size_t)MG_NBASIS * ops->nv_pad * (ops->NBP + ops->NCB), 0.0);
     const double fold[3] = {1.0, 1.0 / (2.0 * dx), 1.0 / (4.0 * dx * dx)};
@@ -554,27 +589,35 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             double* row = ops->basis_host.data() + ((size_t)l * ops->nv_pad + j) * ops->NBP;
             int off = 0;
             for (int q = 0; q < nq; ++q) {
-                for (int o = -R[q]; o <= R[q]; ++o) row[off + o + R[q]] = M[l].V[q].get(j, j + o) * fold[q];
+                for (int o = -R[q]; o <= R[q]; ++o) row[off + o + R[q]] = S[l].V[q].get(j, j + o) * fold[q];
                 off += 2 * R[q] + 1;
             }
-            for (size_t k = 0; k < M[l].W.size(); ++k) {
-                const int sl = slot[M[l].id[k]];
-                if (sl < 0) continue;
-                double* w = row + off + sl * (2 * ops->RW + 1);
-                for (int o = -ops->RW; o <= ops->RW; ++o) w[o + ops->RW] = M[l].W[k].get(j, j + o);
-            }
-            // chain bands, with the 1/(2 dx) of D^x folded in
+            // x-term bands, with the (1/(2 dx))^d of the word's D^x folded in
             double* crow = ops->basis_host.data() + (size_t)MG_NBASIS * ops->nv_pad * ops->NBP +
                            ((size_t)l * ops->nv_pad + j) * ops->NCB;
-            for (size_t k = 0; k < M[l].C.size(); ++k) {
-                if (band_is_zero(M[l].C[k])) continue;
-                int sl = -1;
-                for (size_t c = 0; c < chains.size(); ++c)
-                    if (chains[c].first == M[l].ca[k] && chains[c].second == M[l].cb[k]) sl = (int)c;
-                if (sl < 0) continue;   // only in matrices the order does not use
-                double* w = crow + sl * (2 * MG_XDIAG_RADIUS + 1);
+            for (size_t k = 0; k < S[l].W.size(); ++k) {
+                const int id = S[l].wid[k];
+                const int sl = slot[id];
+                double* w = nullptr;
+                if (sl >= 0) {
+                    w = row + off + sl * (2 * ops->RW + 1);
+                } else {
+                    XWord x;
+                    x.id[0] = id;
+                    const int xs = xterm_slot(x);
+                    if (xs < 0) continue;   // only in matrices the order does not use
+                    w = crow + xs * (2 * MG_XDIAG_RADIUS + 1);
+                }
                 for (int o = -MG_XDIAG_RADIUS; o <= MG_XDIAG_RADIUS; ++o)
-                    w[o + MG_XDIAG_RADIUS] = M[l].C[k].get(j, j + o) / (2.0 * dx);
+                    w[o + MG_XDIAG_RADIUS] = S[l].W[k].get(j, j + o);
+            }
+            for (size_t k = 0; k < S[l].X.size(); ++k) {
+                if (band_is_zero(S[l].X[k])) continue;
+                const int xs = xterm_slot(S[l].xw[k]);
+                if (xs < 0) continue;   // only in matrices the order does not use
+                double* w = crow + xs * (2 * MG_XDIAG_RADIUS + 1);
+                for (int o = -MG_XDIAG_RADIUS; o <= MG_XDIAG_RADIUS; ++o)
+                    w[o + MG_XDIAG_RADIUS] = S[l].X[k].get(j, j + o) * fold[S[l].xw[k].d];
             }
         }
     return MG_OK;

@@ -105,10 +105,10 @@ def test_unsupported_coefficient_combinations_are_reported():
     # a power of D^x with an x-dependent factor
     assert _build_status(wl.langevin_variable_sigma_beta(), 16, 3) == mg.MG_EUNSUPPORTED
     # the paper's variable set: x-dependent noise through d/dv meets D^x in
-    # [B,A] (chains diag(a) D^x diag(b), built at orders 1 and 2); at order 3
-    # a chain meets D^x again
+    # [B,A] (words diag(a) D^x diag(b)) and twice in [[B,A],B] (words
+    # diag(a) D^x diag(b) D^x diag(c)): built at every order
     assert _build_status(wl.langevin_paper_variable(1.1, 0.3), 16, 2) != mg.MG_EUNSUPPORTED
-    assert _build_status(wl.langevin_paper_variable(1.1, 0.3), 16, 3) == mg.MG_EUNSUPPORTED
+    assert _build_status(wl.langevin_paper_variable(1.1, 0.3), 16, 3) != mg.MG_EUNSUPPORTED
     # x-dependent coefficient of an x derivative
     assert _build_status(wl.Coefficients(fx=lambda x, v: -v * (1 + 0.1 * x)), 16, 2) == mg.MG_EUNSUPPORTED
     # g^xx is outside this build

@@ -1,15 +1,18 @@
 """The paper's variable coefficients, eq. (coeffsLangevinVar): diffusion
 a (1 + 1/(x^2+1)) and noise sigma sqrt(1 + 1/(x^2+1)) through d/dv, both
 depending on x, with the transport -v d/dx.  In [B, A] the x derivative meets
-the x-dependent noise, so the Magnus basis holds chains
-C (x) diag(alpha) D^x diag(beta) besides the powers of D^x and the diagonal
-x-factors.  GPU (FP64) against the CPU oracle, which assembles B and A as
-printed in Section 2 (sparse Kronecker products with diag(vec Z)):
+the x-dependent noise once, in [[B,A],B] twice, so the Magnus basis holds
+x-terms C (x) diag(x_0) D^x diag(x_1) (order 2) and
+C (x) diag(x_0) D^x diag(x_1) D^x diag(x_2) (order 3) besides the powers of
+D^x and the diagonal x-factors (order 3: 14 x-terms over 7 x vectors).  GPU
+(FP64) against the CPU oracle, which assembles B and A as printed in
+Section 2 (sparse Kronecker products with diag(vec Z)) and forms the basis by
+sparse products:
 
-  Magnus FP64: 1e-10 relative (Frobenius) and max-norm, orders 1 and 2,
+  Magnus FP64: 1e-10 relative (Frobenius) and max-norm, orders 1 to 3,
   register-resident (nx <= 128) and cooperative (nx <= 512) kernels;
   Euler: 1e-12.
-FP32C and order 3 (chains of chains) are reported unsupported.
+FP32C is reported unsupported for x-terms.
 """
 import math
 import sys
@@ -64,6 +67,12 @@ CASES = [
     ("coop-200x150-m2", 200, 150, 2, 2, 2, 64, 0.002),
     ("coop-256x256-m2", 256, 256, 2, 1, 2, 64, 0.001),
     ("coop-300x200-m2", 300, 200, 2, 1, 2, 64, 0.001),
+    ("res-40x36-m3", 40, 36, 3, 2, 2, 64, 0.02),
+    ("res-100x90-m3", 100, 90, 3, 2, 2, 64, 0.004),
+    ("res-128x128-m3", 128, 128, 3, 2, 3, 96, 0.003),
+    ("coop-200x150-m3", 200, 150, 3, 2, 2, 64, 0.002),
+    ("coop-256x256-m3", 256, 256, 3, 1, 2, 64, 0.001),
+    ("coop-300x200-m3", 300, 200, 3, 1, 2, 64, 0.001),
 ]
 
 
@@ -83,11 +92,12 @@ def test_paper_variable_coefficients_match_oracle(case):
     ops.close()
 
 
-def test_paper_variable_coefficients_full_horizon_gaussian():
-    """The paper's setting at d = 40: Gaussian datum, T = 1, order 2 with
-    h = 0.05 (K = 20), against the oracle."""
-    say("chains 40x40 T=1")
-    n, K, Nf, T, order = 40, 20, 2000, 1.0, 2
+@pytest.mark.parametrize("order", [2, 3])
+def test_paper_variable_coefficients_full_horizon_gaussian(order):
+    """The paper's setting at d = 40: Gaussian datum, T = 1, h = 0.05
+    (K = 20), against the oracle."""
+    say(f"chains 40x40 T=1 order {order}")
+    n, K, Nf, T = 40, 20, 2000, 1.0
     B, A, basis, ops = setup(n, n, order)
     dW = wl.brownian_increments(123, 2, Nf, T=T)
     u0 = wl.gaussian_density(n, n, LO, HI, LO, HI, 1.0).reshape(-1)
@@ -117,17 +127,14 @@ def test_paper_variable_euler_matches_oracle(nx, nv):
     ops.close()
 
 
-def test_chains_unsupported_forms_are_reported():
-    say("chains unsupported")
+@pytest.mark.parametrize("order", [2, 3])
+def test_chains_unsupported_forms_are_reported(order):
+    say(f"chains unsupported, order {order}")
     ops = mg.build_operators(40, 36, LO, HI, LO, HI,
-                             wl.sample_coefficients(COEFFS, 40, 36, LO, HI, LO, HI), 2)
+                             wl.sample_coefficients(COEFFS, 40, 36, LO, HI, LO, HI), order)
     coef = torch.zeros((1, 1, 6), dtype=torch.float64, device=DEV)
     u0 = torch.zeros(40 * 36, dtype=torch.float64, device=DEV)
     with pytest.raises(mg.MagnusError) as ex:
         mg.magnus_expmv(ops, coef, u0, precision="fp32c")
     assert ex.value.code == mg.MG_EUNSUPPORTED
     ops.close()
-    with pytest.raises(mg.MagnusError) as ex:
-        mg.build_operators(40, 36, LO, HI, LO, HI,
-                           wl.sample_coefficients(COEFFS, 40, 36, LO, HI, LO, HI), 3)
-    assert ex.value.code == mg.MG_EUNSUPPORTED
