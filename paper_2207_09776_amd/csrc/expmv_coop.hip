@@ -963,7 +963,10 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
 
 // Workgroup shape per x-width and precision: 8 waves of RJ rows, or, where
 // the FP64 state, halo and factors do not fit 256 registers, 4 waves of twice
-// the rows (one wave per SIMD, which may use 512 registers).  At nx > 512
+// the rows (one wave per SIMD, which may use 512 registers; at nx <= 256 the
+// FP64 kernel without x-factors also runs 4 waves of 16 rows: it spills none
+// of its registers there, against 60 bytes per lane with 8 waves of 8 rows,
+// and its 4096-path 256^2 order-3 launch takes 1955 ms against 2000).  At nx > 512
 // (FP32C only) 4 waves of 6 rows: 24 rows per workgroup, so 43 members hold a
 // 1024-row path where 16-row workgroups need 64, and the exchange, which grows
 // with the member count, costs less.  The rows per workgroup (NW * RJ) depend
@@ -979,7 +982,7 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, true, CALL) }                     \
             } else {                                                                           \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 4, 16, 4, false, CALL) }             \
-                else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, false, CALL) }                    \
+                else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 16, 4, false, CALL) }                   \
             }                                                                                  \
         }                                                                                      \
         if (sh.PX == 8) {                                                                      \

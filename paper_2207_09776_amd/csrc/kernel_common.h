@@ -75,6 +75,26 @@ __device__ inline void dt_apply(const T (&y)[PX], T (&out)[PX]) {
     }
 }
 
+// The raw second difference Dxx = tridiag(1, -2, 1) along x with zero outside
+// the wave, as dt_apply.
+template <int PX, class T>
+__device__ inline void dxx_apply(const T (&y)[PX], T (&out)[PX]) {
+    const T left = from_left<T>(y[PX - 1]);
+    const T right = from_right<T>(y[0]);
+#pragma unroll
+    for (int q = 0; q < PX; ++q) {
+        const T a = (q + 1 < PX) ? y[q + 1] : right;
+        const T b = (q > 0) ? y[q - 1] : left;
+        out[q] = (a + b) - T(2) * y[q];
+    }
+}
+// One letter of an x word: Dt (dxx false) or Dxx (dxx true), wave-uniform.
+template <int PX, class T>
+__device__ inline void letter_apply(bool dxx, const T (&y)[PX], T (&out)[PX]) {
+    if (dxx) dxx_apply<PX, T>(y, out);
+    else dt_apply<PX, T>(y, out);
+}
+
 // Max over the 64 lanes of non-negative values with DPP row shifts and row
 // broadcasts (no LDS traffic); the result is returned wave-uniform (lane 63's
 // value read into scalar registers).
@@ -195,10 +215,12 @@ struct NoChains {
     __device__ double operator()(A...) const { return 0.0; }
 };
 
-// x-terms C_k (x) X_k of row r, added to y.  X_k = diag(x_0) Dt diag(x_1) ...
-// Dt diag(x_d) has depth d <= 2 (Dt without its 1/(2 dx), which the
-// coefficients carry); `xt.desc(k)` is {d, outer, middle, inner} (vector slots
-// of x_0, x_1 and x_d; a depth-0 or depth-1 term has no middle one),
+// x-terms C_k (x) X_k of row r, added to y.  X_k = diag(x_0) L_1 diag(x_1)
+// ... L_d diag(x_d) has depth d <= 2, each letter L_h the raw first difference
+// Dt or second difference Dxx (the coefficients carry 1/(2 dx) and 1/dx^2);
+// `xt.desc(k)` is {d + 4 [L_1 = Dxx] + 8 [L_2 = Dxx], outer, middle, inner}
+// (vector slots of x_0, x_1 and x_d; a depth-0 or depth-1 term has no middle
+// one),
 // `xt.vec(v, q)` vector v at this lane's point q, zero beyond nx, so the next
 // vector cuts every Dt result back to the grid: the truncated matrix product.
 // `ccoef(r, e)` is coefficient e of row r in the x-term section of the table
@@ -224,13 +246,15 @@ __device__ inline void add_xterms(int r, T (&y)[PX], Din din, CCoef ccoef, const
         }
 #pragma unroll
         for (int q = 0; q < PX; ++q) w[q] *= xt.vec(ds.w, q);
-        if (ds.x >= 1) {
+        const int depth = ds.x & 3;
+        if (depth >= 1) {
             T e[PX];
-            dt_apply<PX, T>(w, e);
-            if (ds.x == 2) {
+            // the innermost letter first: L_2 for depth 2, L_1 for depth 1
+            letter_apply<PX, T>(depth == 2 ? ((ds.x >> 3) & 1) : ((ds.x >> 2) & 1), w, e);
+            if (depth == 2) {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) e[q] *= xt.vec(ds.z, q);
-                dt_apply<PX, T>(e, w);
+                letter_apply<PX, T>((ds.x >> 2) & 1, e, w);
             } else {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) w[q] = e[q];

@@ -46,6 +46,7 @@ struct mg_ops {
                                    // x-factors cannot hold, and their coefficients
                                    // per row (NC bands of radius MG_XDIAG_RADIUS)
     int NXV = 0;                   // distinct x vectors of the x-terms
+    bool xt_in_ba = false;         // B or A holds x-terms (no Euler kernel for them)
     // basis tables, host copy and device copy: [MG_NBASIS][nv_pad][NBP], then
     // the x-term section [MG_NBASIS][nv_pad][NCB]
     std::vector<double> basis_host;
@@ -53,7 +54,8 @@ struct mg_ops {
     // x vectors a_t [ND][nx] and per factor {sum, midpoint, half-width, 0};
     // x-term vectors [NXV][nx] (vector 0 is the unit vector) and per x-term
     // {||X||_1, tr X, 0, 0} with D^x taken without its 1/(2 dx);
-    // x-term descriptors [NC][4] = {d, slot of x_0, slot of x_1, slot of x_d}
+    // x-term descriptors [NC][4] = {d + 4 L_1 + 8 L_2, slot of x_0, slot of x_1,
+    // slot of x_d} (letters L: 0 Dt, 1 Dxx)
     std::vector<double> xdiag_host, xstat_host, xchain_host, cstat_host;
     std::vector<int32_t> xdesc_host;
     double* xdiag_dev = nullptr;   // xdiag, xstat, xchain, cstat, xdesc in one allocation

@@ -116,22 +116,38 @@ struct XReg {
     }
 };
 
-// An x word diag(x_0) Dt diag(x_1) ... Dt diag(x_d), d <= 2, with Dt =
-// tridiag(-1, 0, 1) (D^x without its 1/(2 dx)); x_h is a registry id, -1 for
-// the unit vector.
+// An x word diag(x_0) L_1 diag(x_1) ... L_d diag(x_d), d <= 2, whose letters
+// L_h are Dt = tridiag(-1, 0, 1) (D^x without its 1/(2 dx)) or
+// Dxx = tridiag(1, -2, 1) (D^xx without its 1/dx^2); x_h is a registry id,
+// -1 for the unit vector.
 struct XWord {
     int d = 0;
     int id[3] = {-1, -1, -1};
+    int lt[2] = {0, 0};   // letter h+1: 0 Dt, 1 Dxx
     bool unit() const {
         for (int h = 0; h <= d; ++h)
             if (id[h] >= 0) return false;
         return true;
     }
+    // a power of Dt (the V_q tables)
+    bool plain() const {
+        for (int h = 0; h < d; ++h)
+            if (lt[h] != 0) return false;
+        return unit();
+    }
     bool operator==(const XWord& o) const {
         if (d != o.d) return false;
         for (int h = 0; h <= d; ++h)
             if (id[h] != o.id[h]) return false;
+        for (int h = 0; h < d; ++h)
+            if (lt[h] != o.lt[h]) return false;
         return true;
+    }
+    // the factor of the raw letters: (1/(2 dx)) per Dt, 1/dx^2 per Dxx
+    double fold(double dx) const {
+        double f = 1.0;
+        for (int h = 0; h < d; ++h) f *= lt[h] ? 1.0 / (dx * dx) : 1.0 / (2.0 * dx);
+        return f;
     }
 };
 
@@ -160,6 +176,13 @@ struct KOp {
         x.id[0] = xid;
         add(x, B);
     }
+    void add_x(int xid, int letter, const Band& B) {   // B (x) diag(x vector xid) L
+        XWord x;
+        x.d = 1;
+        x.id[0] = xid;
+        x.lt[0] = letter;
+        add(x, B);
+    }
 };
 
 // registry id of the pointwise product of two x vectors (-1: unit)
@@ -185,9 +208,9 @@ bool kop_mul(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
             const XWord& a = X.w[s];
             const XWord& b = Y.w[t];
             if (a.d + b.d > 2) {
-                why = a.unit() && b.unit()
+                why = a.plain() && b.plain()
                           ? "x-derivative power above 2 in the Magnus basis"
-                          : "an x derivative meets x-dependent coefficients more than twice in a "
+                          : "x derivatives and x-dependent coefficients meet more than twice in a "
                             "product of the Magnus basis";
                 return false;
             }
@@ -196,6 +219,8 @@ bool kop_mul(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) {
             for (int h = 0; h < a.d; ++h) c.id[h] = a.id[h];
             c.id[a.d] = xmul(xr, a.id[a.d], b.id[0]);
             for (int h = 1; h <= b.d; ++h) c.id[a.d + h] = b.id[h];
+            for (int h = 0; h < a.d; ++h) c.lt[h] = a.lt[h];
+            for (int h = 0; h < b.d; ++h) c.lt[a.d + h] = b.lt[h];
             Z.add(c, P);
         }
     out = Z;
@@ -212,19 +237,20 @@ bool kop_comm(const KOp& X, const KOp& Y, XReg& xr, KOp& out, std::string& why) 
     return true;
 }
 
-// The x word as an nx x nx band matrix (Dt without its 1/(2 dx)), for the
-// 1-norm and the trace of an x-term.
+// The x word as an nx x nx band matrix (raw letters), for the 1-norm and the
+// trace of an x-term.
 Band word_matrix(const XWord& x, const XReg& xr, int nx) {
     auto vec = [&](int id) {
         return id < 0 ? std::vector<double>((size_t)nx, 1.0) : xr.vecs[id];
     };
-    Band Dt(nx, 1);
+    Band L[2] = {Band(nx, 1), Band(nx, 1)};
     for (int i = 0; i < nx; ++i) {
-        if (i > 0) Dt.set(i, i - 1, -1.0);
-        if (i + 1 < nx) Dt.set(i, i + 1, 1.0);
+        if (i > 0) { L[0].set(i, i - 1, -1.0); L[1].set(i, i - 1, 1.0); }
+        if (i + 1 < nx) { L[0].set(i, i + 1, 1.0); L[1].set(i, i + 1, 1.0); }
+        L[1].set(i, i, -2.0);
     }
     Band M = band_diag(vec(x.id[0]));
-    for (int h = 1; h <= x.d; ++h) M = band_mul(band_mul(M, Dt), band_diag(vec(x.id[h])));
+    for (int h = 1; h <= x.d; ++h) M = band_mul(band_mul(M, L[x.lt[h - 1]]), band_diag(vec(x.id[h])));
     return M;
 }
 
@@ -294,14 +320,12 @@ bool all_zero(const double* c, size_t n) {
 mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops* ops) {
     const int nx = g->nx, nv = g->nv;
     const size_t N = (size_t)nx * nv;
-    if (!all_zero(cf->gxx, N) || !all_zero(cf->sx, N))
-        return mg_fail(MG_EUNSUPPORTED, "g^xx and sigma^x must be zero in this build");
-    // Coefficients of the D^x terms must depend on v only; the others may
-    // depend on x through the low-rank form.
-    enum { H, FX, FV, GXV, GVV, SIG, SV, NCOEF };
-    const double* fields[NCOEF] = {cf->h, cf->fx, cf->fv, cf->gxv, cf->gvv, cf->sig, cf->sv};
-    const char* names[NCOEF] = {"h", "fx", "fv", "gxv", "gvv", "sig", "sv"};
-    const bool x_allowed[NCOEF] = {true, false, true, false, true, true, true};
+    // Every coefficient may depend on x through the low-rank form.
+    enum { H, FX, FV, GXX, GXV, GVV, SIG, SX, SV, NCOEF };
+    const double* fields[NCOEF] = {cf->h,   cf->fx,  cf->fv, cf->gxx, cf->gxv,
+                                   cf->gvv, cf->sig, cf->sx, cf->sv};
+    const char* names[NCOEF] = {"h", "fx", "fv", "gxx", "gxv", "gvv", "sig", "sx", "sv"};
+    (void)N;
     std::vector<double> c[NCOEF];                 // v-only part of each coefficient
     std::vector<std::vector<double>> xb[NCOEF];  // x-dependent terms: b_t(v) ...
     std::vector<int> xid[NCOEF];                 // ... times diag(a_t), registry ids
@@ -309,10 +333,6 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     for (int t = 0; t < NCOEF; ++t) {
         bool nz;
         if (v_only(fields[t], nx, nv, c[t], nz)) continue;
-        if (!x_allowed[t])
-            return mg_fail(MG_EUNSUPPORTED, std::string("coefficient ") + names[t] +
-                                                " multiplies an x derivative and must be finite "
-                                                "and depend on v only in this build");
         for (size_t k = 0; k < N; ++k)
             if (!std::isfinite(fields[t][k]))
                 return mg_fail(MG_EINVAL, std::string("coefficient ") + names[t] + " is not finite");
@@ -345,10 +365,22 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     for (size_t r = 0; r < xb[FV].size(); ++r) B.add_w(xid[FV][r], band_mul(band_diag(xb[FV][r]), Dv));
     for (size_t r = 0; r < xb[GVV].size(); ++r)
         B.add_w(xid[GVV][r], band_axpby(0.5, band_mul(band_diag(xb[GVV][r]), Dvv), 0.0, Dvv));
+    // terms with an x derivative and x-dependent coefficients: words
+    // diag(a) Dt, and the second difference D^xx as the letter Dxx
+    for (size_t r = 0; r < xb[FX].size(); ++r) B.add_x(xid[FX][r], 0, band_diag(xb[FX][r]));
+    for (size_t r = 0; r < xb[GXV].size(); ++r)
+        B.add_x(xid[GXV][r], 0, band_mul(band_diag(xb[GXV][r]), Dv));
+    if (!std::all_of(c[GXX].begin(), c[GXX].end(), [](double v) { return v == 0.0; }))
+        B.add_x(-1, 1, band_axpby(0.5, band_diag(c[GXX]), 0.0, band_diag(c[GXX])));
+    for (size_t r = 0; r < xb[GXX].size(); ++r)
+        B.add_x(xid[GXX][r], 1, band_axpby(0.5, band_diag(xb[GXX][r]), 0.0, band_diag(xb[GXX][r])));
     // A = V_0 (x) I + sum W (x) diag(a)
     A.add_q(0, band_axpby(1.0, band_diag(c[SIG]), 1.0, band_mul(band_diag(c[SV]), Dv)));
     for (size_t r = 0; r < xb[SIG].size(); ++r) A.add_w(xid[SIG][r], band_diag(xb[SIG][r]));
     for (size_t r = 0; r < xb[SV].size(); ++r) A.add_w(xid[SV][r], band_mul(band_diag(xb[SV][r]), Dv));
+    // noise through D^x
+    A.add_q(1, band_diag(c[SX]));
+    for (size_t r = 0; r < xb[SX].size(); ++r) A.add_x(xid[SX][r], 0, band_diag(xb[SX][r]));
 
     const int nact = order == 1 ? 2 : (order == 2 ? 4 : 6);
     KOp M[MG_NBASIS] = {B, A, KOp(nv), KOp(nv), KOp(nv), KOp(nv)};
@@ -374,7 +406,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
         for (auto& b : S[l].V) b = band_zero(nv);
         for (size_t k = 0; k < M[l].w.size(); ++k) {
             const XWord& x = M[l].w[k];
-            if (x.unit()) S[l].V[x.d] = band_axpby(1.0, S[l].V[x.d], 1.0, M[l].V[k]);
+            if (x.plain()) S[l].V[x.d] = band_axpby(1.0, S[l].V[x.d], 1.0, M[l].V[k]);
             else if (x.d == 0) { S[l].wid.push_back(x.id[0]); S[l].W.push_back(M[l].V[k]); }
             else { S[l].xw.push_back(x); S[l].X.push_back(M[l].V[k]); }
         }
@@ -401,7 +433,8 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     auto wword = [&](const XWord& x) {
         double w = 1.0;
         for (int h = 0; h <= x.d; ++h) w *= xmax(x.id[h]);
-        return w * wq[x.d];
+        for (int h = 0; h < x.d; ++h) w *= x.lt[h] ? 4.0 / (dx * dx) : 1.0 / dx;
+        return w;
     };
     std::vector<int> used(xr.vecs.size(), 0);
     std::vector<XWord> xterms;   // distinct x-terms of the active matrices
@@ -447,6 +480,30 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             if (xterm_slot(T.xw[k]) < 0) xterms.push_back(T.xw[k]);
         }
     }
+    // With x-terms the kernels take the V tables of the order-2 band shape
+    // (radii 2 and 1, no Dt^2): a Dt^2 factor, or a Dt factor of radius above
+    // 1, becomes an x-term with unit vectors.
+    if (!xterms.empty()) {
+        for (int q = 1; q < 3; ++q) {
+            if (q == 1 && R[1] <= 1) continue;
+            XWord x;
+            x.d = q;
+            for (int l = 0; l < MG_NBASIS; ++l) {
+                if (band_is_zero(S[l].V[q])) continue;
+                S[l].xw.push_back(x);
+                S[l].X.push_back(S[l].V[q]);
+                S[l].V[q] = band_zero(nv);
+                if (l >= nact) continue;
+                RC = std::max(RC, radius(S[l].X.back()));
+                if (xterm_slot(x) < 0) xterms.push_back(x);
+            }
+            R[q] = 0;
+        }
+    }
+    // Euler reads B and A from the V tables and the diagonal factors only
+    bool xt_in_ba = false;
+    for (int l = 0; l < 2; ++l)
+        for (size_t k = 0; k < S[l].X.size(); ++k) xt_in_ba = xt_in_ba || !band_is_zero(S[l].X[k]);
     // diagonal x-factors in use, numbered in registry order; with x-terms
     // the first MG_MAX_XDIAG keep their own slots (those of B and A, which the
     // Euler kernels read, come first: the coefficients are registered before
@@ -521,6 +578,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     // (unused ones are zero; the variable-coefficient workloads use 3), and
     // with x-terms for 4 factors
     ops->NC = (int)xterms.size();
+    ops->xt_in_ba = xt_in_ba;
     ops->NXV = nxv;
     ops->ND = nd > 0 || ops->NC > 0 ? (nd <= 3 && ops->NC == 0 ? 3 : MG_MAX_XDIAG) : 0;
     ops->RW = ops->ND > 0 ? MG_XDIAG_RADIUS : 0;
@@ -559,7 +617,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     for (int k = 0; k < ops->NC; ++k) {
         const XWord& x = xterms[k];
         int32_t* d = ops->xdesc_host.data() + (size_t)k * 4;
-        d[0] = x.d;
+        d[0] = x.d | (x.lt[0] << 2) | (x.lt[1] << 3);   // depth, letters
         d[1] = vs(x.id[0]);
         d[2] = x.d == 2 ? vs(x.id[1]) : 0;
         d[3] = vs(x.id[x.d]);
@@ -592,7 +650,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
                 for (int o = -R[q]; o <= R[q]; ++o) row[off + o + R[q]] = S[l].V[q].get(j, j + o) * fold[q];
                 off += 2 * R[q] + 1;
             }
-            // x-term bands, with the (1/(2 dx))^d of the word's D^x folded in
+            // x-term bands, with the factors of the word's letters folded in
             double* crow = ops->basis_host.data() + (size_t)MG_NBASIS * ops->nv_pad * ops->NBP +
                            ((size_t)l * ops->nv_pad + j) * ops->NCB;
             for (size_t k = 0; k < S[l].W.size(); ++k) {
@@ -617,7 +675,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
                 if (xs < 0) continue;   // only in matrices the order does not use
                 double* w = crow + xs * (2 * MG_XDIAG_RADIUS + 1);
                 for (int o = -MG_XDIAG_RADIUS; o <= MG_XDIAG_RADIUS; ++o)
-                    w[o + MG_XDIAG_RADIUS] = S[l].X[k].get(j, j + o) * fold[S[l].xw[k].d];
+                    w[o + MG_XDIAG_RADIUS] = S[l].X[k].get(j, j + o) * S[l].xw[k].fold(dx);
             }
         }
     return MG_OK;

@@ -109,10 +109,16 @@ def test_unsupported_coefficient_combinations_are_reported():
     # diag(a) D^x diag(b) D^x diag(c)): built at every order
     assert _build_status(wl.langevin_paper_variable(1.1, 0.3), 16, 2) != mg.MG_EUNSUPPORTED
     assert _build_status(wl.langevin_paper_variable(1.1, 0.3), 16, 3) != mg.MG_EUNSUPPORTED
-    # x-dependent coefficient of an x derivative
-    assert _build_status(wl.Coefficients(fx=lambda x, v: -v * (1 + 0.1 * x)), 16, 2) == mg.MG_EUNSUPPORTED
-    # g^xx is outside this build
-    assert _build_status(wl.Coefficients(gxx=lambda x, v: 1.0 + 0 * x), 16, 2) == mg.MG_EUNSUPPORTED
+    # x-dependent coefficients of x derivatives and the second difference in
+    # x are x-terms (words diag(a) D^x, D^xx), built at every order ...
+    assert _build_status(wl.Coefficients(fx=lambda x, v: -v * (1 + 0.1 * x)), 16, 3) != mg.MG_EUNSUPPORTED
+    assert _build_status(wl.Coefficients(gxx=lambda x, v: 1.0 + 0 * x), 16, 3) != mg.MG_EUNSUPPORTED
+    # ... but x-dependent noise through D^x puts three x derivatives into
+    # [[B,A],A] at order 3
+    sx = wl.Coefficients(fx=lambda x, v: -v, gvv=lambda x, v: 1.0 + 0 * x,
+                         sx=lambda x, v: 0.3 * (1.0 + 0.5 / (1.0 + x * x)) + 0 * v)
+    assert _build_status(sx, 16, 2) != mg.MG_EUNSUPPORTED
+    assert _build_status(sx, 16, 3) == mg.MG_EUNSUPPORTED
     # a coefficient grid of full rank is not a short sum of products b(v) a(x)
     rng = np.random.default_rng(0)
     noise = rng.random((16, 16))
