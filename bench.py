@@ -388,7 +388,7 @@ def run_mixed(args, w):
 
 
 class _Sweep:
-    """Shared set-up of the paper-parameter experiments of Sections 3 and 4:
+    """Shared set-up of the paper-parameter experiments of Sections 3.1, 3.2 and 4:
     a = 1.1, sigma = 1/sqrt(10), [-4, 4]^2, initial datum exp(-(xi^2+eta^2)/2)
     (relative errors do not depend on its scale), M = 100 synthetic paths,
     T = 1, errors Err^{d,4} (kappa = 4).  Times are per path on this GPU (one
@@ -489,7 +489,7 @@ class _Sweep:
 
 
 def sweep_constant_comparison(S):
-    """Section 3, comparison with Euler-Maruyama for d = 100, 200, 300 (the
+    """Section 3.1, comparison with Euler-Maruyama for d = 100, 200, 300 (the
     paper's per-d Magnus step sizes), Lebesgue discretisation 1e-4 (Nf = 10^4
     for T = 1), errors against the closed form.  Paths: seed 11."""
     torch, mg = S.torch, S.mg
@@ -515,7 +515,7 @@ def sweep_constant_comparison(S):
             log(f"d={d} Euler dt={dt:g}: {res[f'E, {dt:g}']}")
         ops.close()
         rows.append(res)
-    return {"experiment": "constant coefficients, comparison with Euler (Section 3)",
+    return {"experiment": "constant coefficients, comparison with Euler (Section 3.1)",
             "paths": S.M, "fine_increments": 10 ** 4, "seed": 11, "results": rows}
 
 
@@ -526,7 +526,7 @@ STEP_SWEEP_K = (120, 100, 80, 60, 50, 40, 30, 25, 20, 16, 15, 12, 10, 8, 6, 5, 4
 
 
 def sweep_constant_steps(S):
-    """Section 3, Figure StepTest: d = 200, orders 2 and 3 over step sizes
+    """Section 3.1, Figure StepTest: d = 200, orders 2 and 3 over step sizes
     h = 1/K, errors against the closed form.  Nf = 12000 (Lebesgue
     discretisation 8.3e-5) so that K = 3..120 divide it.  Paths: seed 12."""
     mg = S.mg
@@ -544,12 +544,12 @@ def sweep_constant_steps(S):
             log(f"steps const d={d}: {r}")
             rows.append(r)
         ops.close()
-    return {"experiment": "constant coefficients, step-size sweep at d = 200 (Figure StepTest)",
+    return {"experiment": "constant coefficients, step-size sweep at d = 200 (Section 3.1, Figure StepTest)",
             "paths": S.M, "fine_increments": STEP_SWEEP_NF, "seed": 12, "results": rows}
 
 
 def sweep_variable(S):
-    """Section 4, eq. (coeffsLangevinVar): Table errorsVar (d = 100, 200, 300;
+    """Section 3.2, eq. (coeffsLangevinVar): Table errorsVar (d = 100, 200, 300;
     Euler 1e-3 and 1e-4 and the Magnus orders at the paper's step sizes,
     against Euler 1e-5) and Figure StepTestVar (d = 200, step-size sweep of
     the Magnus orders against the same reference).  Fine increments at 1e-5
@@ -595,14 +595,14 @@ def sweep_variable(S):
             opm.close()
         ops.close()
         table.append(res)
-    return {"experiment": "variable coefficients (Section 4): Table errorsVar and Figure "
+    return {"experiment": "variable coefficients (Section 3.2): Table errorsVar and Figure "
                           "StepTestVar, against Euler 1e-5",
             "paths": S.M, "fine_increments": 10 ** 5, "magnus_increments": 10 ** 4, "seed": 13,
             "table": table, "step_sweep_d200": sweep}
 
 
 def sweep_d400(S):
-    """Conclusions: constant coefficients at d = 400, order 3 with h = 0.01 and
+    """Section 4 (Conclusions): constant coefficients at d = 400, order 3 with h = 0.01 and
     Lebesgue discretisation 1e-4 against Euler 1e-5 (and 1e-4), errors
     against the closed form.  Fine increments at 1e-5 (Nf = 10^5); Magnus sees
     every tenth node.  Paths: seed 14."""
@@ -628,7 +628,7 @@ def sweep_d400(S):
         log(f"d=400 Euler dt={dt:g}: {res[f'E, {dt:g}']}")
         del u
     ops.close()
-    return {"experiment": "constant coefficients at d = 400 (Conclusions)", "paths": S.M,
+    return {"experiment": "constant coefficients at d = 400 (Section 4, Conclusions)", "paths": S.M,
             "fine_increments": 10 ** 5, "magnus_increments": 10 ** 4, "seed": 14, "results": [res]}
 
 

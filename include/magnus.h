@@ -80,14 +80,17 @@ typedef struct {
 } mg_grid;
 
 /* Coefficient grids of eq. (generalSPDE), host arrays of nx*nv doubles in
- * [nv][nx] order; NULL means identically zero.  This build supports gxx = sx
- * = 0; fx and gxv (the coefficients of x derivatives) depending on v only;
- * h, fv, gvv, sig, sv depending on v, or on x and v when the grid is a sum of
- * at most 4 products b(v) a(x) (to rounding) and no x derivative meets an
- * x-dependent factor in the Magnus basis of the requested order.  That covers
- * the constant- and v-dependent stochastic Langevin SPDE
- * (eq. (coeffsLangevinConst)) at every order and an x,v-dependent diffusion
- * g^vv at orders 1 and 2.  Anything else returns MG_EUNSUPPORTED. */
+ * [nv][nx] order; NULL means identically zero.  Every coefficient may depend
+ * on v, or on x and v when its grid is a sum of at most 4 products b(v) a(x)
+ * (to rounding).  The build supports what the Magnus basis of the requested
+ * order then holds in its factored form: x words diag(x_0) L diag(x_1)
+ * [L diag(x_2)] of at most two letters L (D^x or D^xx) per term, at most 32
+ * such x-terms over 16 distinct x vectors, v bands of radius at most 2 beside
+ * x-dependent factors.  That covers the Langevin SPDE with constant
+ * (eq. (coeffsLangevinConst)) and the paper's variable coefficients
+ * (eq. (coeffsLangevinVar)) at every order, gxx, x-dependent fx and gxv at
+ * every order, sx at orders 1 and 2, and an x,v-dependent diffusion gvv at
+ * orders 1 and 2.  Anything else returns MG_EUNSUPPORTED. */
 typedef struct {
     const double *h, *fx, *fv, *gxx, *gxv, *gvv, *sig, *sx, *sv;
 } mg_coeffs;
@@ -108,10 +111,13 @@ typedef struct mg_ops mg_ops;
  * Builds on the host, in FP64, the drift B and noise A of eq. (SPDEvec) and
  * the commutators needed by Magnus order `order` (1..3) as exact products of
  * the truncated matrices, in the factored form
- *     M_l = sum_{q=0..2} V_{l,q} (x) (D^x)^q + sum_t W_{l,t} (x) diag(a_t),
- * V_{l,q}, W_{l,t} banded nv x nv, a_t the x profiles of the x-dependent
- * coefficients, and uploads the tables to the current HIP device.  Operators
- * with x-dependent factors run on grids up to 128 x 128.
+ *     M_l = sum_{q=0..2} V_{l,q} (x) (D^x)^q + sum_t W_{l,t} (x) diag(a_t)
+ *           + sum_k C_{l,k} (x) X_k,
+ * V_{l,q}, W_{l,t}, C_{l,k} banded nv x nv, a_t the x profiles of the
+ * x-dependent coefficients, X_k the x words that D^x, D^xx and the x profiles
+ * form in the products (see mg_coeffs), and uploads the tables to the current
+ * HIP device.  Operators with x-dependent factors run on grids up to
+ * 512 x 512 (FP64; the FP32C form takes no x-terms).
  *   grid, coeffs : host, read during the call only.
  *   out          : receives a library-owned handle; free with
  *                  mg_free_operators.  The handle is immutable after build and

@@ -758,8 +758,6 @@ mg_status mg_magnus_expmv_multi(const mg_job* jobs, int32_t njobs, void* ws, siz
 namespace {
 // Euler kernel family: resident (nx, nv <= 128) or cooperative (nx <= 512)
 Family euler_family(const mg_ops* ops) {
-    // the Euler kernels take B and A as V tables and diagonal x-factors
-    if (ops->xt_in_ba) return Family::None;
     if (launch_euler_resident(ops, nullptr, 1, nullptr, 1, 0.0, nullptr, nullptr, true) ==
         hipSuccess)
         return Family::Resident;
@@ -790,11 +788,7 @@ mg_status mg_euler_step(const mg_ops* ops, double* u, int64_t P, const double* d
     hipStream_t s = (hipStream_t)stream;
     const Family fam = euler_family(ops);
     if (fam == Family::None)
-        return mg_fail(MG_EUNSUPPORTED,
-                       ops->xt_in_ba ? "mg_euler_step: B or A has x-terms (an x derivative with an "
-                                       "x-dependent coefficient, or D^xx), which the Euler kernels "
-                                       "do not take"
-                                     : "mg_euler_step: no kernel for this grid size");
+        return mg_fail(MG_EUNSUPPORTED, "mg_euler_step: no kernel for this grid size");
     if (P == 0 || NE == 0) return MG_OK;
     if (!u || !dWE) return mg_fail(MG_EINVAL, "mg_euler_step: NULL pointer");
     CoopPlan plan;

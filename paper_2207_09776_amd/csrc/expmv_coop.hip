@@ -83,6 +83,9 @@ struct EulerCoopArgs {
     double dt;
     int32_t* flags;
     const double* xdiag;
+    const double* xchain;  // x-term vectors [nxv][nx] (B or A with x-terms)
+    const int4* xdesc;     // x-term descriptors [nxt]
+    int nxt, nxv;          // x-terms and their vectors (0: none)
     XArea x;
 };
 
@@ -782,7 +785,7 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_split_kernel(CoopArgs a) {
 
 // Euler-Maruyama on the cooperative layout: u <- u + (dt B + dW_n A) u for
 // n = 0..NE-1 (FP64), one group synchronisation per step for the halo rows.
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND, int NC>
 __global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
     using T = double;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
@@ -797,11 +800,24 @@ __global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
     const size_t N = (size_t)nx * nv;
     const int row0 = g * RW + w * RJ;
     const int nrows = min(RJ, max(0, nv - row0));
-    const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(
-        a.xdiag, lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T), lane, nx);
+    T* xl = lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T);
+    const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(a.xdiag, xl, lane, nx);
+    // x-terms of B and A (NC > 0): vectors [nxv][64*PX] after the x vectors,
+    // coefficients in the x-term section of basis matrices 0 and 1
+    T* cvl = xl + (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX : 0);
+    const int ncb = NC > 0 ? a.nxt * (2 * MG_XDIAG_RADIUS + 1) : 0;
+    if constexpr (NC > 0) {
+        for (int idx = threadIdx.x; idx < a.nxv * 64 * PX; idx += 64 * NW) {
+            const int v = idx / (64 * PX), i = idx % (64 * PX);
+            cvl[idx] = i < nx ? a.xchain[(size_t)v * nx + i] : 0.0;
+        }
+    }
+    const XTerms<PX, T> cvec{a.nxt, a.xdesc, cvl, lane};
     __syncthreads();
     const double* Brows = a.basis + (size_t)row0 * NBP;                  // basis matrix 0: B
     const double* Arows = a.basis + ((size_t)a.nv_pad + row0) * NBP;     // basis matrix 1: A
+    const double* Bc = a.basis + (size_t)MG_NBASIS * a.nv_pad * NBP + (size_t)row0 * ncb;
+    const double* Ac = Bc + (size_t)a.nv_pad * ncb;
 
     for (int64_t p = grp; p < a.P && !cg.aborted; p += a.x.ngroups) {
         double* src = a.u + (size_t)p * N;
@@ -836,12 +852,21 @@ __global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
 #pragma unroll
                 for (int q = 0; q < PX; ++q) y[q] += d[r][q];
             };
-            if constexpr (ND == 0)
+            if constexpr (ND == 0) {
                 apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef, lane, nx,
                                                                       emit);
-            else
+            } else if constexpr (NC == 0) {
                 apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
                     d, top, bot, coef, xa, lane, nx, emit);
+            } else {
+                auto ccoef = [&](int r, int e) -> T {
+                    return uniform(fma(a.dt, Bc[r * ncb + e], wn * Ac[r * ncb + e]));
+                };
+                apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T,
+                                decltype(coef), decltype(xa), decltype(emit), NC,
+                                decltype(ccoef), decltype(cvec)>(d, top, bot, coef, xa, lane, nx,
+                                                                 emit, ccoef, cvec);
+            }
         }
         bool bad = false;
 #pragma unroll
@@ -999,7 +1024,8 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
     }
 
 // the Euler kernel exists in FP64 for nx <= 512
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND,
+          int NC = 0>
 hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     if constexpr (F32C || PX > 8) {
         return hipErrorInvalidValue;
@@ -1007,7 +1033,7 @@ hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
         constexpr int RH = halo_rows<R0, R1, R2, ND>();
         *nw = NW;
         *rows = NW * RJ;
-        *fn = (const void*)euler_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
+        *fn = (const void*)euler_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND, NC>;
         *lds = coop_lds_bytes<PX, NW, RH, ND, double>();
         return hipSuccess;
     }
@@ -1037,6 +1063,26 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, co
         if (sh.PX == 4) { if (full) { MG_CHAIN_INFO(4, 16, 4, true) } else { MG_CHAIN_INFO(4, 16, 4, false) } }
         if (sh.PX == 8) { if (full) { MG_CHAIN_INFO(8, 8, 4, true) } else { MG_CHAIN_INFO(8, 8, 4, false) } }
 #undef MG_CHAIN_INFO
+        return hipErrorInvalidValue;
+    }
+    if (kind == CoopKind::Euler && ops->xt_in_ba) {
+        // B or A with x-terms: the x-term Euler kernels (FP64, four x-factors,
+        // the order-2 band shape)
+        if (precision != MG_FP64 || ops->ND != MG_MAX_XDIAG ||
+            !(R[0] == 2 && R[1] == 1 && R[2] == 0 && qmax == 1))
+            return hipErrorInvalidValue;
+        const bool full = ops->grid.nx == 64 * sh.PX;
+        const size_t xv = (size_t)ops->NXV * 64 * sh.PX * sizeof(double);
+#define MG_EULER_XT_INFO(PX, RJ, NW, FX)                                                         \
+    {                                                                                            \
+        const hipError_t e = euler_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, 1>( \
+            fn, lds, nw, rows);                                                                  \
+        *lds += xv;                                                                              \
+        return e;                                                                                \
+    }
+        if (sh.PX == 4) { if (full) { MG_EULER_XT_INFO(4, 16, 4, true) } else { MG_EULER_XT_INFO(4, 16, 4, false) } }
+        if (sh.PX == 8) { if (full) { MG_EULER_XT_INFO(8, 8, 4, true) } else { MG_EULER_XT_INFO(8, 8, 4, false) } }
+#undef MG_EULER_XT_INFO
         return hipErrorInvalidValue;
     }
     if (kind == CoopKind::Euler) {
@@ -1212,6 +1258,10 @@ hipError_t launch_euler_coop(const mg_ops* ops, double* u, int64_t P, const doub
     a.dt = dt;
     a.flags = flags;
     a.xdiag = ops->xdiag_dev;
+    a.xchain = ops->xt_in_ba ? mg_xchain_dev(ops) : nullptr;
+    a.xdesc = ops->xt_in_ba ? mg_xdesc_dev(ops) : nullptr;
+    a.nxt = ops->xt_in_ba ? ops->NC : 0;
+    a.nxv = ops->xt_in_ba ? ops->NXV : 0;
     a.x = xarea_of(xarea, plan);
     const int nfl = plan.ngroups * plan.G;
     hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.x.fl, nfl,

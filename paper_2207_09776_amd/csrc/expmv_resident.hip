@@ -503,11 +503,12 @@ __global__ __launch_bounds__(64 * NW) void expmv_resident_f32c_kernel(
 }
 
 // Euler-Maruyama: u <- u + (dt B + dW_n A) u for n = 0..NE-1 (FP64).
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND, int NC>
 __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     const double* __restrict__ basis, int nx, int nv, int nv_pad, double* __restrict__ u,
     const double* __restrict__ dWE, int NE, double dt, int32_t* __restrict__ flags,
-    const double* __restrict__ xdiag) {
+    const double* __restrict__ xdiag, const double* __restrict__ xvecs,
+    const int4* __restrict__ xdesc, int nxt, int nxv) {
     using T = double;
     using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
@@ -515,6 +516,17 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
     extern __shared__ double lds[];
     Halo<PX, RJ, NW, RH, T> halo{lds};
     int* sflag = reinterpret_cast<int*>(lds + halo_bytes<PX, NW, RH, T>() / sizeof(T));
+    // x-terms of B and A (NC > 0): vectors [nxv][64*PX] after the flag word,
+    // coefficients in the x-term section of basis matrices 0 and 1
+    T* cvl = lds + halo_bytes<PX, NW, RH, T>() / sizeof(T) + 2;
+    const int ncb = NC > 0 ? nxt * (2 * MG_XDIAG_RADIUS + 1) : 0;
+    if constexpr (NC > 0) {
+        for (int idx = threadIdx.x; idx < nxv * 64 * PX; idx += 64 * NW) {
+            const int v = idx / (64 * PX), i = idx % (64 * PX);
+            cvl[idx] = i < nx ? xvecs[(size_t)v * nx + i] : 0.0;
+        }
+    }
+    const XTerms<PX, T> xt{nxt, xdesc, cvl, (int)(threadIdx.x & 63)};
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -546,6 +558,8 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
         }
     const double* Brows = basis + (size_t)row0 * NBP;             // basis matrix 0: B
     const double* Arows = basis + ((size_t)nv_pad + row0) * NBP;  // basis matrix 1: A
+    const double* Bc = basis + (size_t)MG_NBASIS * nv_pad * NBP + (size_t)row0 * ncb;
+    const double* Ac = Bc + (size_t)nv_pad * ncb;
     const double* dw = dWE + (size_t)p * NE;
     int tpar = 0;
     for (int n = 0; n < NE; ++n) {
@@ -585,6 +599,13 @@ __global__ __launch_bounds__(64 * NW) void euler_resident_kernel(
                     // one row and factor at a time (the coefficient sums are VALU work)
                     __builtin_amdgcn_sched_barrier(0);
                 }
+        }
+        if constexpr (NC > 0) {
+            auto ccoef = [&](int r, int e) -> T {
+                return fma(dt, Bc[r * ncb + e], wn * Ac[r * ncb + e]);
+            };
+#pragma unroll
+            for (int r = 0; r < RJ; ++r) add_xterms<PX, MG_XDIAG_RADIUS, T>(r, dn[r], din, ccoef, xt);
         }
 #pragma unroll
         for (int r = 0; r < RJ; ++r)
@@ -667,18 +688,21 @@ hipError_t run_expmv(const mg_ops* ops, const char* tables, size_t tbytes, int64
     return hipGetLastError();
 }
 
-template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND>
+template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, int ND, int NC>
 hipError_t run_euler(const mg_ops* ops, double* u, int64_t P, const double* dWE, int NE,
                      double dt, int32_t* flags, hipStream_t s) {
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>()) return hipErrorInvalidValue;
-    constexpr size_t lds = halo_bytes<PX, NW, RH, double>() + 16;
-    auto kern = euler_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND>;
+    if (ops->NBP != table_stride<R0, R1, R2, QMAX, ND>() || (NC > 0) != ops->xt_in_ba)
+        return hipErrorInvalidValue;
+    const size_t lds = halo_bytes<PX, NW, RH, double>() + 16 +
+                       (NC > 0 ? (size_t)ops->NXV * 64 * PX * sizeof(double) : 0);
+    auto kern = euler_resident_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, ND, NC>;
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     hipLaunchKernelGGL(kern, dim3((unsigned)P), dim3(64 * NW), lds, s, ops->basis_dev,
                        ops->grid.nx, ops->grid.nv, ops->nv_pad, u, dWE, NE, dt, flags,
-                       ops->xdiag_dev);
+                       ops->xdiag_dev, NC > 0 ? mg_xchain_dev(ops) : nullptr,
+                       NC > 0 ? mg_xdesc_dev(ops) : nullptr, ops->NC, ops->NXV);
     return hipGetLastError();
 }
 
@@ -821,7 +845,9 @@ hipError_t launch_euler_resident(const mg_ops* ops, double* u, int64_t P, const 
     const int* R = ops->R;
     const int qmax = ops->qmax;
 #define MG_CALL_EULER(PX, RJ, NW, R0, R1, R2, QM, FX, ND, NC) \
-    run_euler<PX, RJ, NW, R0, R1, R2, 1, FX, ND>(ops, u, P, dWE, NE, dt, flags, s)
+    run_euler<PX, RJ, NW, R0, R1, R2, 1, FX, ND, NC>(ops, u, P, dWE, NE, dt, flags, s)
+    // x-terms in B or A: the x-term kernels of the default shapes
+    if (ops->xt_in_ba) MG_DISPATCH_CHAINS(MG_CALL_EULER)
     MG_DISPATCH(MG_CALL_EULER)
 #undef MG_CALL_EULER
 }

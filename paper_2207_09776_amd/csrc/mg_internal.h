@@ -46,7 +46,7 @@ struct mg_ops {
                                    // x-factors cannot hold, and their coefficients
                                    // per row (NC bands of radius MG_XDIAG_RADIUS)
     int NXV = 0;                   // distinct x vectors of the x-terms
-    bool xt_in_ba = false;         // B or A holds x-terms (no Euler kernel for them)
+    bool xt_in_ba = false;         // B or A holds x-terms (the Euler kernels read them)
     // basis tables, host copy and device copy: [MG_NBASIS][nv_pad][NBP], then
     // the x-term section [MG_NBASIS][nv_pad][NCB]
     std::vector<double> basis_host;

@@ -10,9 +10,9 @@ GPU (FP64) against the CPU oracle, which assembles B and A term by term as in
 Section 2 and forms the basis by sparse products, on data that is O(1) on
 every edge row and column (uniform random u0): 1e-10 relative (Frobenius) and
 max-norm per path, orders 1 to 3 where the basis exists, register-resident
-(40 x 36) and cooperative (200 x 150) kernels.  Reported unsupported:
-sigma^x at order 3 (three x derivatives meet in [[B,A],A]), FP32C, and Euler
-when B or A holds x-terms.
+(40 x 36) and cooperative (200 x 150) kernels; Euler-Maruyama (B and A with
+x-terms) within 1e-12.  Reported unsupported: sigma^x at order 3 (three x
+derivatives meet in [[B,A],A]) and FP32C.
 """
 import sys
 
@@ -23,7 +23,7 @@ torch = pytest.importorskip("torch")
 
 import paper_2207_09776_amd as mg
 import workloads as wl
-from oracle import integrals, magnus, operators
+from oracle import euler, integrals, magnus, operators
 
 pytestmark = pytest.mark.gpu
 
@@ -94,6 +94,30 @@ def test_general_coefficients_match_oracle(case):
     ops.close()
 
 
+@pytest.mark.parametrize("name", list(SETS))
+@pytest.mark.parametrize("nx,nv", [(40, 36), (200, 150)])
+def test_general_coefficients_euler_matches_oracle(name, nx, nv):
+    say(f"general coefficients euler {name} {nx}x{nv}")
+    g = operators.Grid(nx, nv, LO, HI, LO, HI)
+    B, A = operators.drift_and_noise(g, SETS[name][0])
+    ops = build(name, nx, nv, 1)
+    P, NE, T = 2, 16, 0.0004
+    dW = wl.brownian_increments(133, P, 2 * NE, T=T)
+    dWE = integrals.euler_increments(dW, NE)
+    u0 = np.random.default_rng(134).uniform(0.5, 1.5, size=(P, nx * nv))
+    u = to_dev(u0)
+    flags = mg.euler_step(ops, u, to_dev(dWE), T / NE)
+    torch.cuda.synchronize()
+    assert int(flags.abs().sum()) == 0
+    want = np.stack([euler.euler_paths(B, A, u0[p], dWE[p:p + 1], T / NE)[0] for p in range(P)])
+    got = u.cpu().numpy()
+    for p in range(P):
+        fro = np.linalg.norm(got[p] - want[p]) / np.linalg.norm(want[p])
+        mx = np.abs(got[p] - want[p]).max() / np.abs(want[p]).max()
+        assert fro <= 1e-12 and mx <= 1e-12, (name, p, fro, mx)
+    ops.close()
+
+
 def test_general_coefficients_unsupported_forms_are_reported():
     say("general coefficients: unsupported forms")
     with pytest.raises(mg.MagnusError) as ex:
@@ -104,9 +128,5 @@ def test_general_coefficients_unsupported_forms_are_reported():
     u = torch.zeros((1, 40 * 36), dtype=torch.float64, device=DEV)
     with pytest.raises(mg.MagnusError) as ex:
         mg.magnus_expmv(ops, coef, u[0], precision="fp32c")
-    assert ex.value.code == mg.MG_EUNSUPPORTED
-    # B holds the D^xx x-term: no Euler kernel takes it
-    with pytest.raises(mg.MagnusError) as ex:
-        mg.euler_step(ops, u, torch.zeros((1, 4), dtype=torch.float64, device=DEV), 0.01)
     assert ex.value.code == mg.MG_EUNSUPPORTED
     ops.close()
