@@ -242,7 +242,14 @@ mg_status mg_magnus_expmv_noalloc(const mg_ops* ops, const double* coef, int64_t
  * same order), and records the fastest in `ops` for `precision`; later
  * mg_magnus_expmv calls with this ops and precision use it.  Arguments as
  * for mg_magnus_expmv (stats and flags are not written); uT is overwritten.
- * Grids of the cooperative kernel have one shape: the call records nothing.
+ * Register-resident grids: points per lane, rows per wave and waves per
+ * workgroup.  Cooperative grids: the workgroup shapes with the same rows per
+ * workgroup (FP64 at nx <= 256 without x-dependent factors, FP32C at
+ * 256 < nx <= 512); mg_workspace_bytes covers all of them.  Every candidate
+ * must reproduce the default shape's uT bit for bit; one that does not is
+ * excluded (reported).  Other operators
+ * have one shape: the call records nothing.  The choice also enters the
+ * library's autotune cache (mg_autotune_cache_save/load).
  * Unlike the other calls it allocates device memory (a copy of uT) and waits
  * for the stream; do not run it concurrently with other calls that use ops.
  *   reps   : 1..100.
@@ -253,6 +260,24 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
                             const double* u0, int32_t u0_broadcast, double* uT, int32_t precision,
                             double tol, void* ws, size_t ws_bytes, int32_t reps, char* report,
                             size_t report_bytes, void* stream);
+
+/* --------------------------------------------------------------------------
+ * mg_autotune_cache_save / mg_autotune_cache_load  (persisted kernel shapes)
+ *
+ * The library keeps the shapes mg_autotune_expmv picks in a process-wide
+ * cache keyed by the device architecture, the grid, the precision, the order
+ * and the form of the factored operator (band radii, x-factors, x-terms).
+ * mg_build_operators starts every new operator with the cached shapes of its
+ * key.  save writes the whole cache to a text file (first line
+ * "mg-autotune-cache 1", one entry per line); load merges a file written by
+ * save into the cache (operators built earlier are not changed).
+ *   path    : host string, the file.
+ *   entries : nullable; receives the entries written / read.
+ * Errors: MG_EINVAL (NULL path, a file that cannot be opened, a malformed
+ *         line: nothing of that file is merged).  Host-only; thread-safe.
+ * ------------------------------------------------------------------------ */
+mg_status mg_autotune_cache_save(const char* path, int32_t* entries);
+mg_status mg_autotune_cache_load(const char* path, int32_t* entries);
 
 /* --------------------------------------------------------------------------
  * mg_magnus_expmv_multi  (the operation of mg_magnus_expmv for several

@@ -28,7 +28,8 @@ PRECISIONS = {"fp64": MG_FP64, "fp32c": MG_FP32C}
 EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_workspace_bytes", "mg_magnus_expmv", "mg_magnus_expmv_noalloc",
            "mg_workspace_bytes_multi",
-           "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_select_magnus_steps",
+           "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_autotune_cache_save",
+           "mg_autotune_cache_load", "mg_select_magnus_steps",
            "mg_select_magnus_steps_per_path", "mg_iterated_integrals_steps",
            "mg_euler_increments",
            "mg_euler_workspace_bytes",
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mg_iterated_integrals_steps.argtypes = [vp, i64, i64, dbl, vp, i32, i32, vp, vp, vp]
     lib.mg_autotune_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, i32,
                                       ctypes.c_char_p, sz, vp]
+    lib.mg_autotune_cache_save.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+    lib.mg_autotune_cache_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
     lib.mg_workspace_bytes_multi.argtypes = [ctypes.POINTER(mg_job), i32]
     lib.mg_workspace_bytes_multi.restype = sz
     lib.mg_magnus_expmv_multi.argtypes = [ctypes.POINTER(mg_job), i32, vp, sz, vp]
@@ -347,6 +350,22 @@ def autotune_expmv(ops: Operators, coef, u0, precision: str = "fp64", tol: float
         ops.handle, _ptr(coef), P, K, _ptr(u0), bcast, _ptr(uT), PRECISIONS[precision],
         float(tol), _ptr(ws), ws.numel(), int(reps), buf, 1024, _stream(stream)))
     return buf.value.decode()
+
+
+def autotune_cache_save(path: str) -> int:
+    """mg_autotune_cache_save: writes the library's autotune cache; returns
+    the number of entries."""
+    n = ctypes.c_int32(0)
+    _check(load_library().mg_autotune_cache_save(os.fsencode(path), ctypes.byref(n)))
+    return int(n.value)
+
+
+def autotune_cache_load(path: str) -> int:
+    """mg_autotune_cache_load: merges a saved cache into the library's;
+    returns the number of entries read."""
+    n = ctypes.c_int32(0)
+    _check(load_library().mg_autotune_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return int(n.value)
 
 
 @_stream_scoped

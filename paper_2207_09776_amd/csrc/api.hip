@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -70,6 +71,156 @@ const char* mg_last_error(void) { return g_last_error.c_str(); }
 
 const char* mg_version(void) { return "magnus-mi355x 0.1 (gfx950)"; }
 
+namespace {
+// Kernel family for a grid: resident (one workgroup per path) or cooperative.
+enum class Family { None, Resident, Coop };
+Family family_of(const mg_ops* ops, int precision) {
+    if (launch_expmv_resident(ops, nullptr, 0, 1, 1, nullptr, 0, nullptr, 0.0, precision, nullptr,
+                              nullptr, nullptr, true) == hipSuccess)
+        return Family::Resident;
+    if (coop_supported(ops, precision)) return Family::Coop;
+    return Family::None;
+}
+}  // namespace
+
+namespace {
+// ---- autotune cache ---------------------------------------------------------
+// Kernel shapes picked by mg_autotune_expmv, keyed by the device architecture
+// and everything about an operator that decides which kernels and shapes
+// exist and how fast they run: grid, precision, order and the form of the
+// factored operator (band radii, x-factors, x-terms).  New operators with a
+// cached key start with the cached shape; the cache is saved to and loaded
+// from a text file by the caller.
+struct TuneKey {
+    std::string arch;
+    int v[13];
+    bool operator<(const TuneKey& o) const {
+        if (arch != o.arch) return arch < o.arch;
+        return std::lexicographical_compare(v, v + 13, o.v, o.v + 13);
+    }
+};
+struct TuneVal {
+    int fam, a, b, c;   // fam 0: resident shape (PX, RJ, NW); 1: cooperative variant a
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+// the architecture name of a device without its feature suffixes
+void device_arch(int dev, std::string& out) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        out = "unknown";
+        return;
+    }
+    out = prop.gcnArchName;
+    const size_t colon = out.find(':');
+    if (colon != std::string::npos) out.resize(colon);
+}
+
+void tune_key(const mg_ops* ops, int precision, TuneKey& k) {
+    device_arch(ops->device, k.arch);
+    const int v[13] = {ops->grid.nx, ops->grid.nv, precision, ops->order, ops->ND, ops->NC,
+                       ops->NXV,     ops->R[0],   ops->R[1], ops->R[2],  ops->qmax, ops->NBP,
+                       ops->nv_pad};
+    std::copy(v, v + 13, k.v);
+}
+
+// record the operator's tuned shape for `precision`
+void tune_cache_store(const mg_ops* ops, int precision) {
+    const int pi = precision == MG_FP32C ? 1 : 0;
+    TuneVal val{0, 0, 0, 0};
+    if (family_of(ops, precision) == Family::Coop) {
+        val = {1, ops->tuned_coop[pi], 0, 0};
+    } else {
+        const int* t = ops->tuned[pi];
+        if (t[0] == 0) return;
+        val = {0, t[0], t[1], t[2]};
+    }
+    TuneKey k;
+    tune_key(ops, precision, k);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[k] = val;
+}
+
+// start a new operator with the cached shapes of its key
+void tune_cache_apply(mg_ops* ops) {
+    for (int precision : {MG_FP64, MG_FP32C}) {
+        TuneVal val;
+        TuneKey k;
+        tune_key(ops, precision, k);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune.find(k);
+            if (it == g_tune.end()) continue;
+            val = it->second;
+        }
+        const int pi = precision == MG_FP32C ? 1 : 0;
+        if (val.fam == 1) {
+            if (val.a >= 0 && val.a < coop_variants(ops, precision)) ops->tuned_coop[pi] = val.a;
+        } else {
+            int cand[4][3];
+            const int n = resident_candidates(ops->grid.nx, ops->grid.nv, cand, 4);
+            for (int i = 0; i < n; ++i)
+                if (cand[i][0] == val.a && cand[i][1] == val.b && cand[i][2] == val.c) {
+                    ops->tuned[pi][0] = val.a;
+                    ops->tuned[pi][1] = val.b;
+                    ops->tuned[pi][2] = val.c;
+                }
+        }
+    }
+}
+}  // namespace
+
+mg_status mg_autotune_cache_save(const char* path, int32_t* entries) {
+    g_last_error.clear();
+    if (!path) return mg_fail(MG_EINVAL, "mg_autotune_cache_save: NULL path");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE* f = std::fopen(path, "w");
+    if (!f) return mg_fail(MG_EINVAL, std::string("mg_autotune_cache_save: cannot write ") + path);
+    std::fprintf(f, "mg-autotune-cache 1\n");
+    for (const auto& kv : g_tune) {
+        std::fprintf(f, "%s", kv.first.arch.c_str());
+        for (int x : kv.first.v) std::fprintf(f, " %d", x);
+        std::fprintf(f, " %d %d %d %d\n", kv.second.fam, kv.second.a, kv.second.b, kv.second.c);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) return mg_fail(MG_EINVAL, std::string("mg_autotune_cache_save: cannot write ") + path);
+    if (entries) *entries = (int32_t)g_tune.size();
+    return MG_OK;
+}
+
+mg_status mg_autotune_cache_load(const char* path, int32_t* entries) {
+    g_last_error.clear();
+    if (!path) return mg_fail(MG_EINVAL, "mg_autotune_cache_load: NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return mg_fail(MG_EINVAL, std::string("mg_autotune_cache_load: cannot read ") + path);
+    char line[512];
+    std::map<TuneKey, TuneVal> got;
+    bool ok = std::fgets(line, sizeof line, f) && std::strncmp(line, "mg-autotune-cache 1", 19) == 0;
+    while (ok && std::fgets(line, sizeof line, f)) {
+        if (line[0] == '\n' || line[0] == '#') continue;
+        char arch[64];
+        TuneKey k;
+        TuneVal val;
+        const int n = std::sscanf(line, "%63s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d",
+                                  arch, &k.v[0], &k.v[1], &k.v[2], &k.v[3], &k.v[4], &k.v[5],
+                                  &k.v[6], &k.v[7], &k.v[8], &k.v[9], &k.v[10], &k.v[11],
+                                  &k.v[12], &val.fam, &val.a, &val.b, &val.c);
+        if (n != 18 || (val.fam != 0 && val.fam != 1)) {
+            ok = false;
+            break;
+        }
+        k.arch = arch;
+        got[k] = val;
+    }
+    std::fclose(f);
+    if (!ok) return mg_fail(MG_EINVAL, std::string("mg_autotune_cache_load: malformed file ") + path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto& kv : got) g_tune[kv.first] = kv.second;
+    if (entries) *entries = (int32_t)got.size();
+    return MG_OK;
+}
+
 mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32_t order,
                              mg_ops** out) {
     g_last_error.clear();
@@ -122,6 +273,7 @@ mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32
         delete ops;
         return hip_fail(e, "mg_build_operators");
     }
+    tune_cache_apply(ops);
     *out = ops;
     return MG_OK;
 }
@@ -182,25 +334,19 @@ mg_status mg_euler_increments(const double* dW, int64_t P, int64_t Nf, int32_t N
     return e == hipSuccess ? MG_OK : hip_fail(e, "mg_euler_increments");
 }
 
-namespace {
-// Kernel family for a grid: resident (one workgroup per path) or cooperative.
-enum class Family { None, Resident, Coop };
-Family family_of(const mg_ops* ops, int precision) {
-    if (launch_expmv_resident(ops, nullptr, 0, 1, 1, nullptr, 0, nullptr, 0.0, precision, nullptr,
-                              nullptr, nullptr, true) == hipSuccess)
-        return Family::Resident;
-    if (coop_supported(ops, precision)) return Family::Coop;
-    return Family::None;
-}
-}  // namespace
-
 size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t precision) {
     if (!ops || P <= 0 || K <= 0 || (precision != MG_FP64 && precision != MG_FP32C)) return 0;
     size_t bytes = (size_t)P * (size_t)K * mg_table_bytes(ops, precision);
     if (family_of(ops, precision) == Family::Coop) {
+        // the largest exchange area of the workgroup shapes the autotuner may
+        // pick, so that a workspace sized before tuning still fits after it
         CoopPlan plan;
         if (coop_plan(ops, precision, P, &plan) != hipSuccess) return 0;
-        bytes += plan.bytes;
+        size_t xa = plan.bytes;
+        for (int v = 0; v < coop_variants(ops, precision); ++v)
+            if (coop_plan(ops, precision, P, &plan, CoopKind::Expmv, v) == hipSuccess)
+                xa = std::max(xa, plan.bytes);
+        bytes += xa;
     }
     return bytes;
 }
@@ -445,19 +591,28 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
     if (!ws_aligned(ws)) return mg_fail(MG_EINVAL, where + ": workspace not 16-byte aligned");
     if (ws_bytes < c.need)
         return mg_fail(MG_ENOMEM, where + ": workspace smaller than mg_workspace_bytes()");
-    std::string rep;
-    if (c.fam != Family::Resident || ops->NC > 0) {
+    const int pi = precision == MG_FP32C ? 1 : 0;
+    const bool coop = c.fam == Family::Coop;
+    // candidates: workgroup shapes of the register-resident kernel, or shape
+    // variants of the cooperative kernel; all apply the same operations per
+    // point in the same order
+    int cand[4][3];
+    int ncand = 0;
+    if (!coop && ops->NC == 0) ncand = resident_candidates(ops->grid.nx, ops->grid.nv, cand, 4);
+    if (coop) ncand = coop_variants(ops, precision);
+    if (ncand < 2) {
         if (report && report_bytes)
             snprintf(report, report_bytes, "no alternative shapes for this operator and grid");
         return MG_OK;
     }
-    int cand[4][3];
-    const int ncand = resident_candidates(ops->grid.nx, ops->grid.nv, cand, 4);
+    std::string rep;
     hipStream_t s = (hipStream_t)stream;
     char* tables = (char*)ws;
+    const size_t tab_bytes = (size_t)P * K * c.tbytes;
     hipError_t e = launch_assemble(ops, coef, P, K, c.tol, precision, tables, s);
     if (e != hipSuccess) return hip_fail(e, (where + " (assemble)").c_str());
     const size_t N = (size_t)ops->grid.nx * ops->grid.nv;
+    const int tuned_before = ops->tuned_coop[pi];
     double* ref = nullptr;
     unsigned long long* cnt = nullptr;
     hipEvent_t a = nullptr, b = nullptr;
@@ -469,6 +624,23 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
     };
+    // one launch of candidate i (false: it does not fit the workspace)
+    CoopPlan plan;
+    auto launch = [&](int i, bool& fits) -> hipError_t {
+        fits = true;
+        if (!coop)
+            return launch_expmv_resident(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
+                                         precision, nullptr, nullptr, s, false, cand[i]);
+        ops->tuned_coop[pi] = i;
+        hipError_t le = coop_plan(ops, precision, P, &plan);
+        if (le != hipSuccess) return le;
+        if (tab_bytes + plan.bytes > ws_bytes) {
+            fits = false;
+            return hipSuccess;
+        }
+        return launch_expmv_coop(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
+                                 precision, nullptr, nullptr, tables + tab_bytes, plan, s);
+    };
     // the tuning call is not on a hot path: it allocates a reference copy of
     // uT and synchronises the stream
     if ((e = hipMalloc((void**)&ref, (size_t)P * N * sizeof(double))) != hipSuccess ||
@@ -479,9 +651,23 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
     }
     for (int i = 0; i < ncand && e == hipSuccess; ++i) {
         // one launch to warm up (and, for the first shape, the reference result)
-        e = launch_expmv_resident(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
-                                  precision, nullptr, nullptr, s, false, cand[i]);
+        bool fits = true;
+        e = launch(i, fits);
         if (e != hipSuccess) break;
+        char name[96];
+        if (coop) {
+            int nw = 0, rows = 0;
+            (void)coop_variant_shape(ops, precision, i, &nw, &rows);
+            snprintf(name, sizeof name, "variant %d (%d waves of %d rows)", i, nw,
+                     nw ? rows / nw : 0);
+        } else {
+            snprintf(name, sizeof name, "PX=%d RJ=%d NW=%d", cand[i][0], cand[i][1], cand[i][2]);
+        }
+        if (!fits) {
+            rep += std::string(i ? "; " : "") + name + ": workspace too small, skipped";
+            if (i == 0) break;
+            continue;
+        }
         unsigned long long diff = 0;
         if (i == 0) {
             e = hipMemcpyAsync(ref, uT, (size_t)P * N * sizeof(double), hipMemcpyDeviceToDevice, s);
@@ -500,18 +686,16 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
         }
         if (e != hipSuccess) break;
         (void)hipEventRecord(a, s);
-        for (int r = 0; r < reps && e == hipSuccess; ++r)
-            e = launch_expmv_resident(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
-                                      precision, nullptr, nullptr, s, false, cand[i]);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch(i, fits);
         (void)hipEventRecord(b, s);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0.0f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
         if (e != hipSuccess) break;
         ms /= (float)reps;
-        char line[160];
-        snprintf(line, sizeof line, "%sPX=%d RJ=%d NW=%d: %.3f ms%s", i ? "; " : "", cand[i][0],
-                 cand[i][1], cand[i][2], ms, diff ? " (result differs: excluded)" : "");
+        char line[200];
+        snprintf(line, sizeof line, "%s%s: %.3f ms%s", i ? "; " : "", name, ms,
+                 diff ? " (result differs: excluded)" : "");
         rep += line;
         // every candidate computes the same operations per point in the same
         // order, so the results must agree bit for bit
@@ -521,13 +705,24 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
         }
     }
     cleanup();
+    if (coop) ops->tuned_coop[pi] = tuned_before;
     if (e != hipSuccess) return hip_fail(e, where.c_str());
-    int* t = ops->tuned[precision == MG_FP32C ? 1 : 0];
-    t[0] = cand[best][0];
-    t[1] = cand[best][1];
-    t[2] = cand[best][2];
-    rep += "; chosen PX=" + std::to_string(t[0]) + " RJ=" + std::to_string(t[1]) +
-           " NW=" + std::to_string(t[2]);
+    if (best < 0) {
+        if (report && report_bytes) snprintf(report, report_bytes, "%s", rep.c_str());
+        return MG_OK;
+    }
+    if (coop) {
+        ops->tuned_coop[pi] = best;
+        rep += "; chosen variant " + std::to_string(best);
+    } else {
+        int* t = ops->tuned[pi];
+        t[0] = cand[best][0];
+        t[1] = cand[best][1];
+        t[2] = cand[best][2];
+        rep += "; chosen PX=" + std::to_string(t[0]) + " RJ=" + std::to_string(t[1]) +
+               " NW=" + std::to_string(t[2]);
+    }
+    tune_cache_store(ops, precision);
     if (report && report_bytes) snprintf(report, report_bytes, "%s", rep.c_str());
     return MG_OK;
 }

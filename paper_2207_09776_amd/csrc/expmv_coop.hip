@@ -1007,12 +1007,14 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, true, CALL) }                     \
             } else {                                                                           \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 4, 16, 4, false, CALL) }             \
+                else if (variant == 1) { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, false, CALL) }  \
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 16, 4, false, CALL) }                   \
             }                                                                                  \
         }                                                                                      \
         if (sh.PX == 8) {                                                                      \
             if (f32) {                                                                         \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 4, 8, true, CALL) }               \
+                else if (variant == 1) { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 8, 4, true, CALL) }   \
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 4, 8, true, CALL) }                     \
             } else {                                                                           \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 8, 4, false, CALL) }              \
@@ -1039,8 +1041,8 @@ hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     }
 }
 
-hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, const void** fn,
-                             size_t* lds, int* nw, int* rows) {
+hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, int variant,
+                             const void** fn, size_t* lds, int* nw, int* rows) {
     CoopShape sh;
     if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
     const int* R = ops->R;
@@ -1099,10 +1101,17 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, co
 }
 
 // The kernel a call of this kind runs: the difference-first Taylor kernel
-// where one is built for the operator, else the in-place one.
-hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, KInfo* ki) {
-    if (kind == CoopKind::Expmv && split_info(ops, precision, ki) == hipSuccess) return hipSuccess;
-    return coop_info_classic(ops, precision, kind, &ki->fn, &ki->lds, &ki->nw, &ki->rows);
+// where one is built for the operator, else the in-place one; `variant`
+// selects an alternative workgroup shape with the same rows per workgroup
+// and the same arithmetic (coop_variants), -1 the one recorded in the
+// operator by the autotuner.
+hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, KInfo* ki, int variant = -1) {
+    if (kind != CoopKind::Expmv) variant = 0;
+    else if (variant < 0) variant = ops->tuned_coop[precision == MG_FP32C ? 1 : 0];
+    if (kind == CoopKind::Expmv && split_info(ops, precision, ki) == hipSuccess)
+        // the difference-first kernel has no alternative of the same arithmetic
+        return variant == 0 ? hipSuccess : hipErrorInvalidValue;
+    return coop_info_classic(ops, precision, kind, variant, &ki->fn, &ki->lds, &ki->nw, &ki->rows);
 }
 
 }  // namespace
@@ -1124,11 +1133,26 @@ bool coop_supported(const mg_ops* ops, int precision, CoopKind kind) {
     return coop_info(ops, precision, kind, &ki) == hipSuccess;
 }
 
+bool coop_variant_shape(const mg_ops* ops, int precision, int variant, int* nw, int* rows) {
+    KInfo ki;
+    if (coop_info(ops, precision, CoopKind::Expmv, &ki, variant) != hipSuccess) return false;
+    *nw = ki.nw;
+    *rows = ki.rows;
+    return true;
+}
+
+int coop_variants(const mg_ops* ops, int precision) {
+    KInfo ki;
+    if (coop_info(ops, precision, CoopKind::Expmv, &ki, 0) != hipSuccess) return 0;
+    return coop_info(ops, precision, CoopKind::Expmv, &ki, 1) == hipSuccess ? 2 : 1;
+}
+
 // Plan: members per path (G), number of resident groups, exchange-area bytes.
-hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan, CoopKind kind) {
+hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan, CoopKind kind,
+                     int variant) {
     KInfo ki;
     plan->stage = 1;
-    hipError_t e = coop_info(ops, precision, kind, &ki);
+    hipError_t e = coop_info(ops, precision, kind, &ki, variant);
     if (e != hipSuccess) return e;
     const void* fn = ki.fn;
     const size_t lds = ki.lds;

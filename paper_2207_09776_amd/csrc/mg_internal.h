@@ -64,6 +64,8 @@ struct mg_ops {
     // register-resident kernel shape (PX, RJ, NW) recorded by the autotuner
     // per precision (FP64, FP32C); zeros: the default shape
     int tuned[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    // cooperative-kernel shape variant per precision (0: the default)
+    int tuned_coop[2] = {0, 0};
 };
 
 // Per-(path, step) table of the scaled Magnus logarithm (written by the
@@ -146,8 +148,15 @@ struct CoopPlan {
     int stage = 0;   // how far planning got (diagnostics)
     size_t lds = 0, xh_bytes = 0, xn_bytes = 0, fl_bytes = 0, bytes = 0;
 };
+// variant: the workgroup shape (coop_variants), -1 the one the operator records
 hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan,
-                     CoopKind kind = CoopKind::Expmv);
+                     CoopKind kind = CoopKind::Expmv, int variant = -1);
+// Workgroup shapes of the cooperative Taylor kernel for this operator and
+// precision that apply the same arithmetic with the same rows per workgroup
+// (0: no kernel; variant 0 is the default).
+int coop_variants(const mg_ops* ops, int precision);
+// waves and rows per workgroup of a variant (false: none)
+bool coop_variant_shape(const mg_ops* ops, int precision, int variant, int* nw, int* rows);
 hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
                              int K, const double* u0, int u0_broadcast, double* uT, double tol,
                              int precision, int32_t* stats, int32_t* flags, char* xarea,

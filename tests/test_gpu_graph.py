@@ -57,18 +57,23 @@ def test_graph_replays_match_eager():
         assert int(fl.abs().sum()) == 0
 
 
-@pytest.mark.parametrize("n,prec", [(128, "fp64"), (128, "fp32c"), (64, "fp64"), (64, "fp32c")])
+@pytest.mark.parametrize("n,prec", [(128, "fp64"), (128, "fp32c"), (64, "fp64"), (64, "fp32c"),
+                                    (256, "fp64"), (400, "fp32c")])
 def test_autotune_keeps_results(n, prec):
-    """mg_autotune_expmv times the kernel shapes of the grid and records one;
+    """mg_autotune_expmv times the kernel shapes of the grid (register-resident
+    shapes up to 128^2, cooperative workgroup shapes above) and records one;
     results after tuning equal those before bit for bit (every shape applies
-    the same operations in the same order)."""
+    the same operations in the same order; the tuner's own bitwise check
+    excludes a shape that does not)."""
     print(f"autotune {n}^2 {prec}", flush=True)
-    P, K, Nf = 32, 4, 256
+    # cooperative grids: a horizon inside the convergence region of two
+    # Magnus steps (T = 1 would overflow on the finer grids)
+    P, K, Nf, T = (32, 4, 256, 1.0) if n <= 128 else (8, 2, 256, 0.01)
     c = wl.langevin_constant(1.0, 0.5)
     ops = mg.build_operators(n, n, -5, 5, -5, 5, wl.sample_coefficients(c, n, n, -5, 5, -5, 5), 2)
     u0 = torch.from_numpy(wl.gaussian_density(n, n, -5, 5, -5, 5, 0.25).reshape(-1)).to(DEV)
-    dW = torch.from_numpy(wl.brownian_increments(47, P, Nf)).to(DEV)
-    coef, _ = mg.iterated_integrals(dW, 1.0, K, 2)
+    dW = torch.from_numpy(wl.brownian_increments(47, P, Nf, T=T)).to(DEV)
+    coef, _ = mg.iterated_integrals(dW, T, K, 2)
     before, fl, _ = mg.magnus_expmv(ops, coef, u0, precision=prec)
     torch.cuda.synchronize()
     before = before.clone()
@@ -79,6 +84,31 @@ def test_autotune_keeps_results(n, prec):
     torch.cuda.synchronize()
     assert torch.equal(before, after)
     assert int(fl.abs().sum()) == 0 and int(fl2.abs().sum()) == 0
+
+
+def test_autotune_cache_records_the_choice(tmp_path):
+    """The shape the autotuner picks enters the library's cache, which save
+    writes out and load reads back."""
+    print("autotune cache", flush=True)
+    n, P, K = 256, 8, 2
+    c = wl.langevin_constant(1.0, 0.5)
+    ops = mg.build_operators(n, n, -5, 5, -5, 5, wl.sample_coefficients(c, n, n, -5, 5, -5, 5), 3)
+    u0 = torch.from_numpy(wl.gaussian_density(n, n, -5, 5, -5, 5, 0.25).reshape(-1)).to(DEV)
+    dW = torch.from_numpy(wl.brownian_increments(48, P, 256, T=0.05)).to(DEV)
+    coef, _ = mg.iterated_integrals(dW, 0.05, K, 3)
+    rep = mg.autotune_expmv(ops, coef, u0, precision="fp64", reps=2)
+    print(rep, flush=True)
+    assert "chosen variant" in rep, rep
+    chosen = int(rep.rsplit("chosen variant", 1)[1].split()[0])
+    path = tmp_path / "cache.txt"
+    assert mg.autotune_cache_save(str(path)) >= 1
+    lines = path.read_text().splitlines()
+    assert lines[0] == "mg-autotune-cache 1"
+    key = f" {n} {n} 0 3 "
+    mine = [l for l in lines[1:] if key in l]
+    assert mine and mine[-1].split()[-4:] == ["1", str(chosen), "0", "0"], (mine, chosen)
+    assert mg.autotune_cache_load(str(path)) == len(lines) - 1
+    ops.close()
 
 
 def test_graph_replays_cooperative_and_multi_job():
