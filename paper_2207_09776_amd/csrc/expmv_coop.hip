@@ -903,9 +903,13 @@ struct CoopShape {
 };
 
 // x points per lane
-bool pick_coop_shape(int nx, CoopShape& sh) {
+bool pick_coop_shape(int nx, CoopShape& sh, int precision = MG_FP64) {
     if (nx <= 128) return false;
     if (nx <= 256) { sh.PX = 4; return true; }
+    // FP64 between 256 and 384 points: 5 or 6 points per lane instead of 8
+    // (less padding, and fewer registers for the x-term form)
+    if (precision == MG_FP64 && nx <= 320) { sh.PX = 5; return true; }
+    if (precision == MG_FP64 && nx <= 384) { sh.PX = 6; return true; }
     if (nx <= 512) { sh.PX = 8; return true; }
     if (nx <= 1024) { sh.PX = 16; return true; }
     return false;
@@ -955,7 +959,8 @@ hipError_t split_kernel_info(KInfo* ki) {
 // grids up to 256 points wide with coefficients that depend on v only.
 hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
     CoopShape sh;
-    if (precision != MG_FP32C || ops->ND != 0 || !pick_coop_shape(ops->grid.nx, sh) || sh.PX != 4)
+    if (precision != MG_FP32C || ops->ND != 0 || !pick_coop_shape(ops->grid.nx, sh, precision) ||
+        sh.PX != 4)
         return hipErrorInvalidValue;
     const bool full = ops->grid.nx == 64 * sh.PX;
     const int* R = ops->R;
@@ -1011,6 +1016,14 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 16, 4, false, CALL) }                   \
             }                                                                                  \
         }                                                                                      \
+        if (sh.PX == 5 && !f32) {                                                              \
+            if (nd) { MG_COOP_SHAPES_ND(5, 8, 4, false, false, CALL) }                         \
+            else { MG_COOP_SHAPES(5, 8, 4, false, false, CALL) }                               \
+        }                                                                                      \
+        if (sh.PX == 6 && !f32) {                                                              \
+            if (nd) { MG_COOP_SHAPES_ND(6, 8, 4, false, false, CALL) }                         \
+            else { MG_COOP_SHAPES(6, 8, 4, false, false, CALL) }                               \
+        }                                                                                      \
         if (sh.PX == 8) {                                                                      \
             if (f32) {                                                                         \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 4, 8, true, CALL) }               \
@@ -1044,9 +1057,15 @@ hipError_t euler_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
 hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, int variant,
                              const void** fn, size_t* lds, int* nw, int* rows) {
     CoopShape sh;
-    if (!pick_coop_shape(ops->grid.nx, sh)) return hipErrorInvalidValue;
+    if (!pick_coop_shape(ops->grid.nx, sh, precision)) return hipErrorInvalidValue;
     const int* R = ops->R;
     const int qmax = ops->qmax;
+    // alternative shapes exist for the Taylor kernel without x-dependent
+    // factors, FP64 at 4 points per lane and FP32C at 8
+    if (variant != 0 &&
+        !(kind == CoopKind::Expmv && ops->ND == 0 && ops->NC == 0 &&
+          ((precision == MG_FP64 && sh.PX == 4) || (precision == MG_FP32C && sh.PX == 8))))
+        return hipErrorInvalidValue;
     if (kind == CoopKind::Expmv && ops->NC > 0) {
         // x-terms: FP64, four x-factors, the order-2 band shape, the FP64
         // x-factor workgroup shapes; the x-term vectors add to the LDS
@@ -1063,6 +1082,8 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, in
         return e;                                                                                \
     }
         if (sh.PX == 4) { if (full) { MG_CHAIN_INFO(4, 16, 4, true) } else { MG_CHAIN_INFO(4, 16, 4, false) } }
+        if (sh.PX == 5) { MG_CHAIN_INFO(5, 8, 4, false) }
+        if (sh.PX == 6) { MG_CHAIN_INFO(6, 8, 4, false) }
         if (sh.PX == 8) { if (full) { MG_CHAIN_INFO(8, 8, 4, true) } else { MG_CHAIN_INFO(8, 8, 4, false) } }
 #undef MG_CHAIN_INFO
         return hipErrorInvalidValue;
@@ -1083,6 +1104,8 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, in
         return e;                                                                                \
     }
         if (sh.PX == 4) { if (full) { MG_EULER_XT_INFO(4, 16, 4, true) } else { MG_EULER_XT_INFO(4, 16, 4, false) } }
+        if (sh.PX == 5) { MG_EULER_XT_INFO(5, 8, 4, false) }
+        if (sh.PX == 6) { MG_EULER_XT_INFO(6, 8, 4, false) }
         if (sh.PX == 8) { if (full) { MG_EULER_XT_INFO(8, 8, 4, true) } else { MG_EULER_XT_INFO(8, 8, 4, false) } }
 #undef MG_EULER_XT_INFO
         return hipErrorInvalidValue;
@@ -1120,7 +1143,9 @@ int coop_rows_max(int nx) {
     CoopShape sh;
     if (!pick_coop_shape(nx, sh)) return 0;
     // the most rows per workgroup of any shape instantiated for this x width
-    return sh.PX == 4 ? 64 : sh.PX == 8 ? 32 : 24;
+    // (5, 6 and 8 points per lane: 32 rows, the FP32C shapes of these widths
+    // included)
+    return sh.PX == 4 ? 64 : sh.PX == 16 ? 24 : 32;
 }
 
 int coop_table_rows(int nx, int nv) {
@@ -1197,7 +1222,7 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     plan->lds = lds;
     plan->threads = 64 * nw;
     CoopShape sh;
-    pick_coop_shape(ops->grid.nx, sh);
+    pick_coop_shape(ops->grid.nx, sh, precision);
     plan->xh_bytes = ((size_t)ngroups * G * 2 * 2 * kRHX * (64 * sh.PX) * elem + 255) & ~(size_t)255;
     plan->xn_bytes = ((size_t)ngroups * G * 2 * nw * 2 * sizeof(double) + 255) & ~(size_t)255;
     plan->fl_bytes = ((size_t)ngroups * G * sizeof(int) + 256 + 255) & ~(size_t)255;

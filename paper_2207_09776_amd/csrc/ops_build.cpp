@@ -587,21 +587,37 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     ops->NB = (2 * R[0] + 1) + (2 * R[1] + 1) + (nq == 3 ? 2 * R[2] + 1 : 0) +
               ops->ND * (2 * ops->RW + 1);
     ops->NBP = (ops->NB + 1) & ~1;
+    // Diagonal x-factors as midpoint plus deviation: W (x) diag(a) =
+    // (m W) (x) I + W (x) diag(a - m) with m the midpoint of a.  The first part
+    // joins the V0 band (in FP64, here) wherever every W of that factor fits
+    // the V0 radius, so the kernels multiply only the deviation: in the FP32
+    // form a point's diagonal is then not the near-cancelling sum of two large
+    // rounded parts (the trace-shifted V0 centre and the full x-factor).
+    std::vector<double> xmid(ops->ND, 0.0);
     ops->xdiag_host.assign((size_t)ops->ND * nx, 0.0);
     ops->xstat_host.assign((size_t)ops->ND * 4, 0.0);
     for (size_t k = 0; k < xr.vecs.size(); ++k) {
         if (slot[k] < 0) continue;
         const std::vector<double>& a = xr.vecs[k];
-        double sum = 0.0, lo = a[0], hi = a[0];
+        double lo = a[0], hi = a[0];
         for (int i = 0; i < nx; ++i) {
-            ops->xdiag_host[(size_t)slot[k] * nx + i] = a[i];
-            sum += a[i];
             lo = std::min(lo, a[i]);
             hi = std::max(hi, a[i]);
         }
+        bool fits = true;
+        for (int l = 0; l < MG_NBASIS; ++l)
+            for (size_t t = 0; t < S[l].W.size(); ++t)
+                if (S[l].wid[t] == (int)k && radius(S[l].W[t]) > R[0]) fits = false;
+        const double m = fits ? 0.5 * (hi + lo) : 0.0;
+        xmid[slot[k]] = m;
+        double sum = 0.0;
+        for (int i = 0; i < nx; ++i) {
+            ops->xdiag_host[(size_t)slot[k] * nx + i] = a[i] - m;
+            sum += a[i] - m;
+        }
         double* st = ops->xstat_host.data() + (size_t)slot[k] * 4;
         st[0] = sum;                 // for the trace
-        st[1] = 0.5 * (hi + lo);     // midpoint and half-width of the values,
+        st[1] = 0.5 * (hi + lo) - m; // midpoint and half-width of the values,
         st[2] = 0.5 * (hi - lo);     // for the 1-norm bound
     }
     // x-term vectors [NXV][nx], descriptors {d, outer, middle, inner} and per
@@ -649,6 +665,12 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
             for (int q = 0; q < nq; ++q) {
                 for (int o = -R[q]; o <= R[q]; ++o) row[off + o + R[q]] = S[l].V[q].get(j, j + o) * fold[q];
                 off += 2 * R[q] + 1;
+            }
+            // the midpoints of the diagonal x-factors, in V0
+            for (size_t k = 0; k < S[l].W.size(); ++k) {
+                const int sl = slot[S[l].wid[k]];
+                if (sl < 0 || xmid[sl] == 0.0) continue;
+                for (int o = -R[0]; o <= R[0]; ++o) row[o + R[0]] += xmid[sl] * S[l].W[k].get(j, j + o);
             }
             // x-term bands, with the factors of the word's letters folded in
             double* crow = ops->basis_host.data() + (size_t)MG_NBASIS * ops->nv_pad * ops->NBP +

@@ -73,6 +73,7 @@ CASES = [
     ("coop-200x150-m3", 200, 150, 3, 2, 2, 64, 0.002),
     ("coop-256x256-m3", 256, 256, 3, 1, 2, 64, 0.001),
     ("coop-300x200-m3", 300, 200, 3, 1, 2, 64, 0.001),
+    ("coop-350x120-m3", 350, 120, 3, 1, 2, 64, 0.001),
 ]
 
 

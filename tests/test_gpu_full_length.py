@@ -4,14 +4,17 @@ single paths whose FP64 oracle values were written once by
 tests/golden/make_full_length.py (oracle/ only, seeded inputs of workloads/).
 
   FP64 Magnus: 1e-10 relative (Frobenius over the grid) and max-norm;
-  FP32C:       1e-5 relative and max-norm for constant coefficients; 3e-5 with
-               x-dependent coefficients, where each point's diagonal is the
-               sum of two large FP32 parts that nearly cancel (the trace shift
-               in the x-independent band, the diffusion centre in the
-               x-factors): their rounding leaves about 2^-24 ||Y_k|| per
-               Magnus step, about 2^-24 ||Y_k|| sqrt(K) = 1.7e-5 over the
-               K = 256 steps of the 512^2 workload (1.3e-5 measured on 16
-               paths, the same on all of them).
+  FP32C:       1e-5 relative and max-norm for constant coefficients; with
+               x-dependent coefficients 1e-5 relative and 2e-5 max-norm.  The
+               x-factors of the basis carry only their deviation from the
+               midpoint of their range (the midpoint itself is folded into
+               the x-independent band in FP64 on the host), so what is left
+               is the trace shift of that band, a large FP32 diagonal part
+               that nearly cancels: its rounding leaves about 2^-24 ||Y_k||
+               per Magnus step at the points of largest diffusion, whose
+               accumulation over the K = 256 steps of the 512^2 workload
+               gives the max-norm its margin over the Frobenius figure
+               (6.4e-6 relative, 1.3e-5 max-norm measured).
 """
 import glob
 import json
@@ -58,11 +61,11 @@ def batch(d):
     return ops, coef, u0
 
 
-def check(got, want, tol, what):
+def check(got, want, tol, what, tol_max=None):
     fro = np.linalg.norm(got - want) / np.linalg.norm(want)
     mx = np.abs(got - want).max() / np.abs(want).max()
     say(f"{what}: relative {fro:.2e}, max-norm {mx:.2e}")
-    assert fro <= tol and mx <= tol, (what, fro, mx)
+    assert fro <= tol and mx <= (tol if tol_max is None else tol_max), (what, fro, mx)
 
 
 def test_records_present():
@@ -86,8 +89,8 @@ def test_full_length_path_matches_oracle(name):
         torch.cuda.synchronize()
         p = d["path"]
         assert int(flags[p]) == 0
-        tol = 1e-10 if prec == "fp64" else (3e-5 if d["coefficients"].startswith("variable")
-                                            else 1e-5)
-        check(uT[p].cpu().numpy().reshape(want.shape), want, tol, f"{name} {prec}")
+        tol = 1e-10 if prec == "fp64" else 1e-5
+        tol_max = 2e-5 if prec == "fp32c" and d["coefficients"].startswith("variable") else tol
+        check(uT[p].cpu().numpy().reshape(want.shape), want, tol, f"{name} {prec}", tol_max)
         del uT, flags
     ops.close()

@@ -302,6 +302,11 @@ COOP_CASES = [
     ("coop-256x256-m2-f64", 256, 256, -5.0, 5.0, 2, 3, 2, 256, 0.25, "fp64", 1e-10),
     ("coop-256x256-m3-f64", 256, 256, -5.0, 5.0, 3, 2, 2, 256, 0.25, "fp64", 1e-10),
     ("coop-200x150-m2-f64", 200, 150, -5.0, 5.0, 2, 2, 2, 256, 0.25, "fp64", 1e-10),
+    # FP64 between 256 and 384 points per row: 5 and 6 points per lane, the
+    # last lane partly empty; order 3 and a ragged last slab
+    ("coop-300x100-m3-f64", 300, 100, -5.0, 5.0, 3, 2, 2, 256, 0.05, "fp64", 1e-10),
+    ("coop-350x90-m2-f64", 350, 90, -5.0, 5.0, 2, 2, 2, 256, 0.05, "fp64", 1e-10),
+    ("coop-384x70-m3-f64", 384, 70, -5.0, 5.0, 3, 2, 2, 256, 0.05, "fp64", 1e-10),
     ("coop-256x256-m2-f32c", 256, 256, -5.0, 5.0, 2, 3, 2, 256, 0.25, "fp32c", 1e-5),
     ("coop-512x512-m2-f32c", 512, 512, -5.0, 5.0, 2, 1, 1, 64, 0.05, "fp32c", 1e-5),
     # nx > 512: workgroups of 24 rows; 520 leaves most of the last lane's 16
