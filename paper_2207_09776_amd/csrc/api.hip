@@ -156,7 +156,7 @@ void tune_cache_apply(mg_ops* ops) {
         }
         const int pi = precision == MG_FP32C ? 1 : 0;
         if (val.fam == 1) {
-            if (val.a >= 0 && val.a < coop_variants(ops, precision)) ops->tuned_coop[pi] = val.a;
+            if (coop_variant_valid(ops, precision, val.a)) ops->tuned_coop[pi] = val.a;
         } else {
             int cand[4][3];
             const int n = resident_candidates(ops->grid.nx, ops->grid.nv, cand, 4);
@@ -343,8 +343,9 @@ size_t mg_workspace_bytes(const mg_ops* ops, int64_t P, int32_t K, int32_t preci
         CoopPlan plan;
         if (coop_plan(ops, precision, P, &plan) != hipSuccess) return 0;
         size_t xa = plan.bytes;
-        for (int v = 0; v < coop_variants(ops, precision); ++v)
-            if (coop_plan(ops, precision, P, &plan, CoopKind::Expmv, v) == hipSuccess)
+        for (int v = 0; v < MG_COOP_VARIANTS; ++v)
+            if (coop_variant_valid(ops, precision, v) &&
+                coop_plan(ops, precision, P, &plan, CoopKind::Expmv, v) == hipSuccess)
                 xa = std::max(xa, plan.bytes);
         bytes += xa;
     }
@@ -597,9 +598,17 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
     // variants of the cooperative kernel; all apply the same operations per
     // point in the same order
     int cand[4][3];
+    int cv[MG_COOP_VARIANTS];   // cooperative variants that plan on this device
     int ncand = 0;
     if (!coop && ops->NC == 0) ncand = resident_candidates(ops->grid.nx, ops->grid.nv, cand, 4);
-    if (coop) ncand = coop_variants(ops, precision);
+    if (coop) {
+        CoopPlan vp;
+        for (int v = 0; v < MG_COOP_VARIANTS; ++v)
+            if (coop_variant_valid(ops, precision, v) &&
+                coop_plan(ops, precision, P, &vp, CoopKind::Expmv, v) == hipSuccess)
+                cv[ncand++] = v;
+        if (ncand > 0 && cv[0] != 0) ncand = 0;   // the default is the reference
+    }
     if (ncand < 2) {
         if (report && report_bytes)
             snprintf(report, report_bytes, "no alternative shapes for this operator and grid");
@@ -631,7 +640,7 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
         if (!coop)
             return launch_expmv_resident(ops, tables, c.tbytes, P, K, u0, u0_broadcast, uT, c.tol,
                                          precision, nullptr, nullptr, s, false, cand[i]);
-        ops->tuned_coop[pi] = i;
+        ops->tuned_coop[pi] = cv[i];
         hipError_t le = coop_plan(ops, precision, P, &plan);
         if (le != hipSuccess) return le;
         if (tab_bytes + plan.bytes > ws_bytes) {
@@ -657,9 +666,9 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
         char name[96];
         if (coop) {
             int nw = 0, rows = 0;
-            (void)coop_variant_shape(ops, precision, i, &nw, &rows);
-            snprintf(name, sizeof name, "variant %d (%d waves of %d rows)", i, nw,
-                     nw ? rows / nw : 0);
+            (void)coop_variant_shape(ops, precision, cv[i], &nw, &rows);
+            snprintf(name, sizeof name, "variant %d (%d waves of %d rows%s)", cv[i], nw,
+                     nw ? rows / nw : 0, (cv[i] & 2) ? ", overlapped exchange" : "");
         } else {
             snprintf(name, sizeof name, "PX=%d RJ=%d NW=%d", cand[i][0], cand[i][1], cand[i][2]);
         }
@@ -712,8 +721,8 @@ mg_status mg_autotune_expmv(mg_ops* ops, const double* coef, int64_t P, int32_t 
         return MG_OK;
     }
     if (coop) {
-        ops->tuned_coop[pi] = best;
-        rep += "; chosen variant " + std::to_string(best);
+        ops->tuned_coop[pi] = cv[best];
+        rep += "; chosen variant " + std::to_string(cv[best]);
     } else {
         int* t = ops->tuned[pi];
         t[0] = cand[best][0];

@@ -138,6 +138,40 @@ struct HaloC {
     }
 };
 
+// LDS halo between the waves of a cooperative workgroup, double buffered by
+// term parity: wave w writes its first RH rows to [par][w][0..RH) and its last
+// RH rows to [par][w][RH..2RH).
+template <int PX, int RJ, int NW, int RH, class T>
+struct HaloX {
+    T* base;
+    __device__ T* slot(int par, int w, int s) const {
+        return base + (((size_t)par * NW + w) * (2 * RH) + s) * (64 * PX);
+    }
+    __device__ void publish(int par, int w, int lane, const T (&d)[RJ][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) {
+                slot(par, w, s)[lane * PX + q] = d[s][q];
+                slot(par, w, RH + s)[lane * PX + q] = d[RJ - RH + s][q];
+            }
+    }
+    // rows -RH..-1 from wave w-1 (w > 0)
+    __device__ void fetch_top(int par, int w, int lane, T (&top)[RH][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) top[s][q] = slot(par, w - 1, RH + s)[lane * PX + q];
+    }
+    // rows RJ..RJ+RH-1 from wave w+1 (w < NW-1)
+    __device__ void fetch_bot(int par, int w, int lane, T (&bot)[RH][PX]) const {
+#pragma unroll
+        for (int s = 0; s < RH; ++s)
+#pragma unroll
+            for (int q = 0; q < PX; ++q) bot[s][q] = slot(par, w + 1, s)[lane * PX + q];
+    }
+};
+
 // One workgroup's view of its group: slab index g, group index grp, the
 // exchange through the workspace and the count of group synchronisations.
 // Per synchronisation: every wave publishes (publish_edges, publish_pair) and
@@ -283,6 +317,49 @@ struct CoopGroup {
         out[1] = uniform(o1);
     }
     __device__ __forceinline__ void next() { ++counter; }
+
+    // Overlapped exchange (expmv_coop_kernel with OVL): one counter per wave,
+    // [ngroups][G][NW] after the group's member counters are unused.  A wave
+    // bumps its counter once its own stores of the sync have completed, and
+    // every wave polls all counters of its group itself, so neither needs a
+    // workgroup barrier.
+    __device__ __forceinline__ void bump_wave() const {
+        if (lane == 0) xstore(x.fl + ((size_t)grp * x.G + g) * NW + w, counter + 1);
+    }
+    // false: the launch was aborted (spin limit here or elsewhere)
+    __device__ __forceinline__ bool poll_waves() const {
+        const int* cnt = x.fl + (size_t)grp * x.G * NW;
+        const int n = x.G * NW;
+        for (int spins = 0;; ++spins) {
+            bool ready = true;
+            for (int mm = lane; mm < n; mm += 64)
+                if (xload(cnt + mm) < counter + 1) ready = false;
+            if (__all(ready)) return true;
+            if (spins > kSpinLimit || xload(x.abort_word)) {
+                if (lane == 0) xstore(x.abort_word, 1);
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    // end of a path, overlapped form: every wave publishes its flag with its
+    // pair, no workgroup barrier
+    __device__ __forceinline__ bool any_member_waves(bool mine) {
+        if (aborted) return false;
+        publish_pair(__any(mine) ? 1.0 : 0.0, 0.0);
+        wait_stores();
+        bump_wave();
+        if (!poll_waves()) {
+            if (lane == 0) sh[0] = 1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            aborted = true;
+            return false;
+        }
+        double got[2];
+        read_pairs(got);
+        next();
+        return got[0] != 0.0;
+    }
     // end of a path: combine a per-workgroup flag over the group (nonzero if
     // any member set it)
     __device__ __forceinline__ bool any_member(bool mine) {
@@ -310,9 +387,14 @@ constexpr bool xa_in_lds() {
 // LDS: halo | abort word (16 bytes) | x vectors [ND][64*PX] (when in LDS) |
 // x-term vectors [nxv][64*PX] (their count is known at launch only: the
 // launch adds them)
-template <int PX, int NW, int RH, int ND, class T>
+// (the overlapped form keeps two halo buffers, alternating per term)
+template <int PX, int NW, int RH, int ND, class T, bool OVL = false>
+constexpr size_t coop_halo_elems() {
+    return (size_t)(OVL ? 2 : 1) * NW * 2 * RH * 64 * PX;
+}
+template <int PX, int NW, int RH, int ND, class T, bool OVL = false>
 constexpr size_t coop_lds_bytes() {
-    return (size_t)NW * 2 * RH * 64 * PX * sizeof(T) + 16 +
+    return coop_halo_elems<PX, NW, RH, ND, T, OVL>() * sizeof(T) + 16 +
            (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX * sizeof(T) : 0);
 }
 
@@ -356,7 +438,7 @@ struct XVec<PX, ND, true, T> {
 };
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND,
-          int NC>
+          int NC, bool OVL>
 __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
@@ -364,17 +446,21 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     // x-term coefficients per row (NC > 0: the operator has x-terms)
     const int ncb = NC > 0 ? a.nxt * (2 * MG_XDIAG_RADIUS + 1) : 0;
     constexpr int RW = NW * RJ;
+    constexpr size_t HE = coop_halo_elems<PX, NW, RH, ND, T, OVL>();
     extern __shared__ double lds_d[];
     T* lds = reinterpret_cast<T*>(lds_d);
     HaloC<PX, RJ, NW, RH, T> halo{lds};
-    CoopGroup<PX, RJ, NW, RH, T> cg(a.x, a.nx, reinterpret_cast<int*>(lds + (size_t)NW * 2 * RH * 64 * PX));
+    HaloX<PX, RJ, NW, RH, T> halo2{lds};
+    int* sh = reinterpret_cast<int*>(lds + HE);
+    CoopGroup<PX, RJ, NW, RH, T> cg(a.x, a.nx, sh);
     const int lane = cg.lane, w = cg.w, g = cg.g, grp = cg.grp;
     const int nx = a.nx, nv = a.nv;
     const size_t N = (size_t)nx * nv;
     const int row0 = g * RW + w * RJ;                 // first global row of this wave
     const int nrows = min(RJ, max(0, nv - row0));
+    if (threadIdx.x == 0) sh[0] = 0;
     // the x vectors of the x-dependent factors at this lane's points
-    T* xl = lds + (size_t)NW * 2 * RH * 64 * PX + 16 / sizeof(T);
+    T* xl = lds + HE + 16 / sizeof(T);
     const XVec<PX, ND, xa_in_lds<ND, T>(), T> xa(a.xdiag, xl, lane, nx);
     // x-term vectors [nxv][64*PX] in LDS after the x vectors
     T* cvl = xl + (xa_in_lds<ND, T>() ? (size_t)ND * 64 * PX : 0);
@@ -387,20 +473,38 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     const XTerms<PX, T> cvec{a.nxt, a.xdesc, cvl, lane};
     __syncthreads();
 
-    // one application of the operator to this wave's rows, in place
-    auto apply_term = [&](T (&d)[RJ][PX], const T (&top)[RH][PX], const T (&bot)[RH][PX],
-                          auto coef, auto ccoef, auto emit) {
+    // one application of the operator to this wave's rows, in place (for
+    // the overlapped exchange in the segmented order, with a hook)
+    auto apply_dir = [&](auto seg, T (&d)[RJ][PX], const T (&top)[RH][PX],
+                         const T (&bot)[RH][PX], auto coef, auto ccoef, auto emit, auto hook) {
+        constexpr bool SEG = decltype(seg)::value;
         if constexpr (ND == 0)
-            apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(d, top, bot, coef, lane, nx,
-                                                                  emit);
+            apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T, decltype(coef), decltype(emit),
+                          SEG, decltype(hook)>(d, top, bot, coef, lane, nx, emit, hook);
         else if constexpr (NC == 0)
-            apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T>(
-                d, top, bot, coef, xa, lane, nx, emit);
+            apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T,
+                            decltype(coef), decltype(xa), decltype(emit), 0, NoChains, NoChains,
+                            SEG, decltype(hook)>(d, top, bot, coef, xa, lane, nx, emit,
+                                                 NoChains{}, NoChains{}, hook);
         else
             apply_inplace_x<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, ND, MG_XDIAG_RADIUS, T,
                             decltype(coef), decltype(xa), decltype(emit), NC, decltype(ccoef),
-                            decltype(cvec)>(d, top, bot, coef, xa, lane, nx, emit, ccoef, cvec);
+                            decltype(cvec), SEG, decltype(hook)>(d, top, bot, coef, xa, lane, nx,
+                                                                 emit, ccoef, cvec, hook);
     };
+    auto apply_term = [&](T (&d)[RJ][PX], const T (&top)[RH][PX], const T (&bot)[RH][PX],
+                          auto coef, auto ccoef, auto emit) {
+        apply_dir(std::false_type{}, d, top, bot, coef, ccoef, emit, NoHook{});
+    };
+    // overlapped exchange: in the segmented order no halo row is read before
+    // step RJ - 2RH; the wave bumps its counter before step IB, and before
+    // step IP polls the group, then loads the halo rows (LDS and the
+    // neighbours') and the norms, which arrive while steps IP .. RJ - 2RH - 1
+    // are computed
+    constexpr int IP = (RJ - 2 * RH - 3) > 1 ? (RJ - 2 * RH - 3) : 1;
+    constexpr int IB = IP / 2;
+    static_assert(!OVL || (RJ > 2 * RH && IP <= RJ - 2 * RH), "overlapped exchange needs RJ > 2 RH");
+    int hb = 0;   // LDS halo buffer of the overlapped form (alternates per term)
 
     for (int64_t p = grp; p < a.P && !cg.aborted; p += a.x.ngroups) {
         // state F (+ compensation L for the FP32 form)
@@ -446,6 +550,93 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                 double pr0 = (double)uniform(sm), pr1 = 0.0;
                 double c1 = 0.0;
                 T fj = 1;
+                if constexpr (OVL) {
+                    for (int j = 1; j <= m; ++j) {
+                        // publish c_{j-1} (LDS halo, edge rows, norms)
+                        halo2.publish(hb, w, lane, d);
+                        cg.publish_edges(d);
+                        cg.publish_pair(pr0, pr1);
+                        __syncthreads();
+                        if (sh[0]) {
+                            cg.aborted = true;
+                            break;
+                        }
+                        T top[RH][PX], bot[RH][PX];
+                        const int buf = hb;
+                        hb ^= 1;
+                        double got[2] = {0.0, 0.0};
+                        auto hook = [&](int i) {
+                            if (i == IB) {
+                                wait_stores();
+                                cg.bump_wave();
+                            }
+                            if (i == IP) {
+                                if (w > 0) halo2.fetch_top(buf, w, lane, top);
+                                if (w + 1 < NW) halo2.fetch_bot(buf, w, lane, bot);
+                                if (cg.poll_waves()) {
+                                    cg.load_edges(top, bot);
+                                    cg.read_pairs(got);
+                                } else {
+#pragma unroll
+                                    for (int s2 = 0; s2 < RH; ++s2)
+#pragma unroll
+                                        for (int q = 0; q < PX; ++q) top[s2][q] = bot[s2][q] = T(0);
+                                    if (lane == 0) sh[0] = 1;
+                                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                                    cg.aborted = true;
+                                }
+                                cg.next();
+                            }
+                        };
+                        // c_j = Y c_{j-1} in place (not yet scaled or summed)
+                        auto raw = [](int, T (&)[PX]) {};
+                        apply_dir(std::true_type{}, d, top, bot, coef, ccoef, raw, hook);
+                        if (cg.aborted) break;
+                        // the stop rule on the norms of c_{j-1} and F_{j-1}, as
+                        // below: a stop discards c_j
+                        if (j == 1) {
+                            c1 = got[0];
+                        } else {
+                            const double c2 = got[0], fn = got[1];
+                            if (c1 + c2 <= a.tol * fn) break;
+                            c1 = c2;
+                        }
+                        T mc = 0, mf = 0;
+                        if constexpr (F32C) {
+                            const T invj = uniform((float)(1.0 / (double)j));
+                            const T invj_lo = uniform((float)(1.0 / (double)j - (double)invj));
+#pragma unroll
+                            for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                                for (int q = 0; q < PX; ++q) {
+                                    const T x = fma(d[r][q], invj, d[r][q] * invj_lo);
+                                    d[r][q] = x;
+                                    const T yy = x + L[r][q];
+                                    const T t = F[r][q] + yy;
+                                    L[r][q] = yy - (t - F[r][q]);
+                                    F[r][q] = t;
+                                    mc = max_abs(mc, x);
+                                    mf = max_abs(mf, t);
+                                }
+                            mc = wave_max(mc);
+                        } else {
+                            fj /= (T)j;
+#pragma unroll
+                            for (int r = 0; r < RJ; ++r)
+#pragma unroll
+                                for (int q = 0; q < PX; ++q) {
+                                    F[r][q] = fma(d[r][q], fj, F[r][q]);
+                                    mc = max_abs(mc, d[r][q]);
+                                    mf = max_abs(mf, F[r][q]);
+                                }
+                            mc = wave_max(mc) * fj;
+                        }
+                        mf = wave_max(mf);
+                        pr0 = (double)mc;
+                        pr1 = (double)mf;
+                        ++terms;
+                    }
+                } else
                 for (int j = 1; j <= m; ++j) {
                     halo.publish(w, lane, d);
                     cg.publish_edges(d);
@@ -541,12 +732,17 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
                     bad |= !isfinite(u);
                 }
             }
-        const bool any_bad = cg.any_member(bad);
+        const bool any_bad = OVL ? cg.any_member_waves(bad) : cg.any_member(bad);
         if (a.flags && g == 0 && threadIdx.x == 0) {
             int f = pflag | (any_bad ? MG_FLAG_NONFINITE : 0);
             if (cg.aborted) f |= MG_FLAG_ABORT;
             a.flags[p] = f;
         }
+    }
+    if constexpr (OVL) {
+        // a wave that gave up marks the word; the others learn of it here
+        __syncthreads();
+        if (sh[0]) cg.aborted = true;
     }
     if (cg.aborted && a.flags && threadIdx.x == 0) {
         // mark every path this group had not finished
@@ -571,40 +767,6 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
 // 4096-path order-3 workload): in FP64 the two term arrays, the partial sum
 // and the difference windows of four points per lane need more than the 256
 // registers of a wave in an 8-wave workgroup.
-
-// LDS halo between the waves of a cooperative workgroup, double buffered by
-// term parity: wave w writes its first RH rows to [par][w][0..RH) and its last
-// RH rows to [par][w][RH..2RH).
-template <int PX, int RJ, int NW, int RH, class T>
-struct HaloX {
-    T* base;
-    __device__ T* slot(int par, int w, int s) const {
-        return base + (((size_t)par * NW + w) * (2 * RH) + s) * (64 * PX);
-    }
-    __device__ void publish(int par, int w, int lane, const T (&d)[RJ][PX]) const {
-#pragma unroll
-        for (int s = 0; s < RH; ++s)
-#pragma unroll
-            for (int q = 0; q < PX; ++q) {
-                slot(par, w, s)[lane * PX + q] = d[s][q];
-                slot(par, w, RH + s)[lane * PX + q] = d[RJ - RH + s][q];
-            }
-    }
-    // rows -RH..-1 from wave w-1 (w > 0)
-    __device__ void fetch_top(int par, int w, int lane, T (&top)[RH][PX]) const {
-#pragma unroll
-        for (int s = 0; s < RH; ++s)
-#pragma unroll
-            for (int q = 0; q < PX; ++q) top[s][q] = slot(par, w - 1, RH + s)[lane * PX + q];
-    }
-    // rows RJ..RJ+RH-1 from wave w+1 (w < NW-1)
-    __device__ void fetch_bot(int par, int w, int lane, T (&bot)[RH][PX]) const {
-#pragma unroll
-        for (int s = 0; s < RH; ++s)
-#pragma unroll
-            for (int q = 0; q < PX; ++q) bot[s][q] = slot(par, w + 1, s)[lane * PX + q];
-    }
-};
 
 // LDS of the difference-first kernel: halo [2][NW][2RH] rows | abort word (16
 // bytes) | FP32 form: the workgroup's coefficient rows of the current step
@@ -916,15 +1078,20 @@ bool pick_coop_shape(int nx, CoopShape& sh, int precision = MG_FP64) {
 }
 
 template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, bool F32C, int ND,
-          int NC = 0>
+          int NC = 0, bool OVL = false>
 hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    *nw = NW;
-    *rows = NW * RJ;
-    *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND, NC>;
-    *lds = coop_lds_bytes<PX, NW, RH, ND, T>();
-    return hipSuccess;
+    if constexpr (OVL && RJ <= 2 * RH) {
+        // the overlapped exchange needs rows that read no halo row
+        return hipErrorInvalidValue;
+    } else {
+        *nw = NW;
+        *rows = NW * RJ;
+        *fn = (const void*)expmv_coop_kernel<PX, RJ, NW, R0, R1, R2, QMAX, FULLX, F32C, ND, NC, OVL>;
+        *lds = coop_lds_bytes<PX, NW, RH, ND, T, OVL>();
+        return hipSuccess;
+    }
 }
 
 // A cooperative Taylor kernel: entry, LDS, waves and rows per workgroup.
@@ -1012,7 +1179,7 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, true, CALL) }                     \
             } else {                                                                           \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 4, 16, 4, false, CALL) }             \
-                else if (variant == 1) { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, false, CALL) }  \
+                else if (variant & 1) { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 8, 8, false, CALL) }   \
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 4, 16, 4, false, CALL) }                   \
             }                                                                                  \
         }                                                                                      \
@@ -1027,7 +1194,7 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
         if (sh.PX == 8) {                                                                      \
             if (f32) {                                                                         \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 4, 8, true, CALL) }               \
-                else if (variant == 1) { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 8, 4, true, CALL) }   \
+                else if (variant & 1) { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 8, 4, true, CALL) }    \
                 else { MG_COOP_FULLX(MG_COOP_SHAPES, 8, 4, 8, true, CALL) }                     \
             } else {                                                                           \
                 if (nd) { MG_COOP_FULLX(MG_COOP_SHAPES_ND, 8, 8, 4, false, CALL) }              \
@@ -1060,12 +1227,16 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, in
     if (!pick_coop_shape(ops->grid.nx, sh, precision)) return hipErrorInvalidValue;
     const int* R = ops->R;
     const int qmax = ops->qmax;
-    // alternative shapes exist for the Taylor kernel without x-dependent
-    // factors, FP64 at 4 points per lane and FP32C at 8
-    if (variant != 0 &&
-        !(kind == CoopKind::Expmv && ops->ND == 0 && ops->NC == 0 &&
+    // alternative shapes (bit 0) exist for the Taylor kernel without
+    // x-dependent factors, FP64 at 4 points per lane and FP32C at 8; the
+    // overlapped exchange (bit 1) for every Taylor kernel of the default shape
+    if (variant < 0 || variant >= MG_COOP_VARIANTS) return hipErrorInvalidValue;
+    const bool ovl = (variant & 2) != 0;
+    if ((variant & 1) &&
+        !(kind == CoopKind::Expmv && ops->ND == 0 && ops->NC == 0 && !ovl &&
           ((precision == MG_FP64 && sh.PX == 4) || (precision == MG_FP32C && sh.PX == 8))))
         return hipErrorInvalidValue;
+    if (ovl && kind != CoopKind::Expmv) return hipErrorInvalidValue;
     if (kind == CoopKind::Expmv && ops->NC > 0) {
         // x-terms: FP64, four x-factors, the order-2 band shape, the FP64
         // x-factor workgroup shapes; the x-term vectors add to the LDS
@@ -1076,8 +1247,11 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, in
         const size_t xv = (size_t)ops->NXV * 64 * sh.PX * sizeof(double);
 #define MG_CHAIN_INFO(PX, RJ, NW, FX)                                                            \
     {                                                                                            \
-        const hipError_t e = coop_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, 1>( \
-            fn, lds, nw, rows);                                                                  \
+        const hipError_t e =                                                                     \
+            ovl ? coop_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, 1, true>(     \
+                      fn, lds, nw, rows)                                                         \
+                : coop_kernel_info<PX, RJ, NW, 2, 1, 0, 1, FX, false, MG_MAX_XDIAG, 1, false>(    \
+                      fn, lds, nw, rows);                                                        \
         *lds += xv;                                                                              \
         return e;                                                                                \
     }
@@ -1117,17 +1291,17 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, in
         MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
     }
-#define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND) \
-    coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND>(fn, lds, nw, rows)
+#define MG_CALL_INFO(PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND)                                   \
+    (ovl ? coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND, 0, true>(fn, lds, nw, rows)  \
+         : coop_kernel_info<PX, RJ, NW, R0, R1, R2, QM, FX, F32, ND, 0, false>(fn, lds, nw, rows))
     MG_COOP_DISPATCH(MG_CALL_INFO)
 #undef MG_CALL_INFO
 }
 
 // The kernel a call of this kind runs: the difference-first Taylor kernel
 // where one is built for the operator, else the in-place one; `variant`
-// selects an alternative workgroup shape with the same rows per workgroup
-// and the same arithmetic (coop_variants), -1 the one recorded in the
-// operator by the autotuner.
+// selects a variant with the same rows per workgroup and the same arithmetic
+// (coop_variant_valid), -1 the one recorded in the operator by the autotuner.
 hipError_t coop_info(const mg_ops* ops, int precision, CoopKind kind, KInfo* ki, int variant = -1) {
     if (kind != CoopKind::Expmv) variant = 0;
     else if (variant < 0) variant = ops->tuned_coop[precision == MG_FP32C ? 1 : 0];
@@ -1166,10 +1340,10 @@ bool coop_variant_shape(const mg_ops* ops, int precision, int variant, int* nw, 
     return true;
 }
 
-int coop_variants(const mg_ops* ops, int precision) {
+bool coop_variant_valid(const mg_ops* ops, int precision, int variant) {
     KInfo ki;
-    if (coop_info(ops, precision, CoopKind::Expmv, &ki, 0) != hipSuccess) return 0;
-    return coop_info(ops, precision, CoopKind::Expmv, &ki, 1) == hipSuccess ? 2 : 1;
+    return variant >= 0 && variant < MG_COOP_VARIANTS &&
+           coop_info(ops, precision, CoopKind::Expmv, &ki, variant) == hipSuccess;
 }
 
 // Plan: members per path (G), number of resident groups, exchange-area bytes.
@@ -1225,7 +1399,9 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     pick_coop_shape(ops->grid.nx, sh, precision);
     plan->xh_bytes = ((size_t)ngroups * G * 2 * 2 * kRHX * (64 * sh.PX) * elem + 255) & ~(size_t)255;
     plan->xn_bytes = ((size_t)ngroups * G * 2 * nw * 2 * sizeof(double) + 255) & ~(size_t)255;
-    plan->fl_bytes = ((size_t)ngroups * G * sizeof(int) + 256 + 255) & ~(size_t)255;
+    // counters: one per wave (the overlapped exchange; the other kernels use
+    // the first ngroups * G), then the abort word
+    plan->fl_bytes = ((size_t)ngroups * G * nw * sizeof(int) + 256 + 255) & ~(size_t)255;
     plan->bytes = plan->xh_bytes + plan->xn_bytes + plan->fl_bytes;
     return hipSuccess;
 }
@@ -1236,7 +1412,7 @@ XArea xarea_of(char* xarea, const CoopPlan& plan) {
     x.xh = xarea;
     x.xn = reinterpret_cast<double*>(xarea + plan.xh_bytes);
     x.fl = reinterpret_cast<int*>(xarea + plan.xh_bytes + plan.xn_bytes);
-    x.abort_word = x.fl + (size_t)plan.ngroups * plan.G;
+    x.abort_word = x.fl + (size_t)plan.ngroups * plan.G * (plan.threads / 64);
     x.G = plan.G;
     x.ngroups = plan.ngroups;
     x.xcd_map = plan.xcd_map;
@@ -1274,7 +1450,7 @@ hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbyte
     a.nxv = ops->NXV;
     a.nv_pad = ops->nv_pad;
     a.x = xarea_of(xarea, plan);
-    const int nfl = plan.ngroups * plan.G;
+    const int nfl = plan.ngroups * plan.G * (plan.threads / 64);
     hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.x.fl, nfl,
                        a.x.abort_word);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1312,7 +1488,7 @@ hipError_t launch_euler_coop(const mg_ops* ops, double* u, int64_t P, const doub
     a.nxt = ops->xt_in_ba ? ops->NC : 0;
     a.nxv = ops->xt_in_ba ? ops->NXV : 0;
     a.x = xarea_of(xarea, plan);
-    const int nfl = plan.ngroups * plan.G;
+    const int nfl = plan.ngroups * plan.G * (plan.threads / 64);
     hipLaunchKernelGGL(coop_reset_kernel, dim3((nfl + 255) / 256), dim3(256), 0, s, a.x.fl, nfl,
                        a.x.abort_word);
     if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -3,6 +3,7 @@
 // operator, LDS halo slots and the per-(path, step) table view.
 #pragma once
 
+#include <type_traits>
 #include <cmath>
 
 #include "mg_internal.h"
@@ -286,30 +287,50 @@ struct XTerms {
 // time.  `coef(r, e)` is the coefficient e of local row r; rows beyond nv have
 // zero coefficients in the (padded) tables, so they produce zeros without a
 // branch.  QMAX is the highest power of Dt present.
+// SEG computes rows RH .. RJ-1 first and rows 0 .. RH-1 last (each row's
+// arithmetic is the same; the old values of rows RH .. 2RH-1, which the last
+// rows read, are kept when those rows are committed), so that neither halo
+// is read before step RJ - 2RH.  `hook(i)` runs before the i-th row computed;
+// the cooperative kernel uses it to take part in its group's exchange while
+// the rows that do not need the halo rows are computed.  `emit` may take the
+// row's input accessor as a third argument (it reads the kept rows).
+struct NoHook {
+    __device__ void operator()(int) const {}
+};
 template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, class T,
-          class Coef, class Emit>
+          class Coef, class Emit, bool SEG = false, class Hook = NoHook>
 __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
                                      const T (&bot)[RH][PX], Coef coef, int lane, int nx,
-                                     Emit emit) {
+                                     Emit emit, Hook hook = Hook{}) {
     using BD = Bands<R0, R1, R2, QMAX>;
     constexpr int NB = BD::NB;
-    auto din = [&](int rr, int q) -> T {
-        if (rr < 0) return top[rr + RH][q];
-        if (rr >= RJ) return bot[rr - RJ][q];
-        return d[rr][q];
+    static_assert(!SEG || RJ > 2 * RH, "segmented order needs more than 2 RH rows");
+    // row computed at step i
+    auto row_at = [](int i) -> int {
+        return SEG ? (i < RJ - RH ? RH + i : i - (RJ - RH)) : i;
     };
     T res[RJ][PX];
+    T keep[RH][PX];   // SEG: old rows RH .. 2RH-1
     // coefficients of the current row; the next row's are loaded while the
     // current one is computed (scheduling barriers keep the scalar loads from
     // being hoisted all at once)
     T cur[NB], nxt[NB];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) cur[e] = coef(0, e);
+    for (int e = 0; e < NB; ++e) cur[e] = coef(row_at(0), e);
 #pragma unroll
-    for (int r = 0; r < RJ; ++r) {
-        if (r + 1 < RJ) {
+    for (int i = 0; i < RJ; ++i) {
+        const int r = row_at(i);
+        const bool last_seg = SEG && i >= RJ - RH;
+        auto din = [&](int rr, int q) -> T {
+            if (rr < 0) return top[rr + RH][q];
+            if (rr >= RJ) return bot[rr - RJ][q];
+            if (last_seg && rr >= RH && rr < 2 * RH) return keep[rr - RH][q];
+            return d[rr][q];
+        };
+        hook(i);
+        if (i + 1 < RJ) {
 #pragma unroll
-            for (int e = 0; e < NB; ++e) nxt[e] = coef(r + 1, e);
+            for (int e = 0; e < NB; ++e) nxt[e] = coef(row_at(i + 1), e);
         }
         T y0[PX], y1[PX], y2[PX];
 #pragma unroll
@@ -349,24 +370,51 @@ __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
 #pragma unroll
         for (int q = 0; q < PX; ++q)
             if (!FULLX && lane * PX + q >= nx) y0[q] = T(0);
-        emit(r, y0);
+        if constexpr (std::is_invocable_v<Emit, int, T (&)[PX], decltype(din)>)
+            emit(r, y0, din);
+        else
+            emit(r, y0);
 #pragma unroll
         for (int q = 0; q < PX; ++q) res[r][q] = y0[q];
-        if (r >= RH) {
+        if constexpr (SEG) {
+            // the row is computed here: without this the hook's control flow
+            // lets the rows before it sink past it, where their operands
+            // then stay live (the register file overflows)
 #pragma unroll
-            for (int q = 0; q < PX; ++q) d[r - RH][q] = res[r - RH][q];
+            for (int q = 0; q < PX; ++q) asm volatile("" : "+v"(res[r][q]));
         }
-        if (r + 1 < RJ) {
+        // commit row k once no row still to be computed reads its old value
+        auto commit = [&](int k) {
+            if (SEG && k >= RH && k < 2 * RH) {
+#pragma unroll
+                for (int q = 0; q < PX; ++q) keep[k - RH][q] = d[k][q];
+            }
+#pragma unroll
+            for (int q = 0; q < PX; ++q) d[k][q] = res[k][q];
+        };
+        if (!SEG && r >= RH) commit(r - RH);
+        if (SEG && !last_seg) {
+            if (r - RH >= RH) commit(r - RH);
+            if (i == RJ - RH - 1) {
+#pragma unroll
+                for (int k = (RJ - RH > RH ? RJ - RH : RH); k < RJ; ++k) commit(k);
+            }
+        }
+        if (i + 1 < RJ) {
 #pragma unroll
             for (int e = 0; e < NB; ++e) cur[e] = nxt[e];
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+    // the last RH rows computed
+    constexpr int rlo = SEG ? 0 : (RJ > RH ? RJ - RH : 0);
+    constexpr int rhi = SEG ? RH : RJ;
 #pragma unroll
-    for (int r = (RJ > RH ? RJ - RH : 0); r < RJ; ++r)
+    for (int r = rlo; r < rhi; ++r)
 #pragma unroll
         for (int q = 0; q < PX; ++q) d[r][q] = res[r][q];
 }
+
 
 // apply_inplace with x-dependent factors: every factor W_t (x) diag(a_t) adds
 // a_t(x) * sum_b W_t[j][b] d(j+b) to row j before it is emitted (a_t at this
@@ -374,22 +422,19 @@ __device__ inline void apply_inplace(T (&d)[RJ][PX], const T (&top)[RH][PX],
 // coefficients are requested at the start of the row.  Row r is emitted before
 // apply_inplace overwrites d[r - RH], so the rows r - RW .. r + RW read here
 // are still the input (RW <= RH).
+// The rows are read through the accessor apply_inplace hands to the emit
+// (in its SEG order it reads the kept rows).
 template <int PX, int RJ, int R0, int R1, int R2, int QMAX, bool FULLX, int RH, int ND, int RW,
           class T, class Coef, class XA, class Emit, int NC = 0, class CCoef = NoChains,
-          class CVec = NoChains>
+          class CVec = NoChains, bool SEG = false, class Hook = NoHook>
 __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
                                        const T (&bot)[RH][PX], Coef coef, XA xa, int lane, int nx,
-                                       Emit emit, CCoef ccoef = CCoef{}, CVec cvec = CVec{}) {
+                                       Emit emit, CCoef ccoef = CCoef{}, CVec cvec = CVec{},
+                                       Hook hook = Hook{}) {
     constexpr int NBM = Bands<R0, R1, R2, QMAX>::NB;
     constexpr int WL = 2 * RW + 1;
     static_assert(RW <= RH, "halo narrower than the x-dependent factors");
-    apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T>(
-        d, top, bot, coef, lane, nx, [&](int r, T (&y)[PX]) {
-            auto din = [&](int rr, int q) -> T {
-                if (rr < 0) return top[rr + RH][q];
-                if (rr >= RJ) return bot[rr - RJ][q];
-                return d[rr][q];
-            };
+    auto xemit = [&](int r, T (&y)[PX], auto din) {
             T w[ND][WL];
 #pragma unroll
             for (int t = 0; t < ND; ++t)
@@ -409,7 +454,9 @@ __device__ inline void apply_inplace_x(T (&d)[RJ][PX], const T (&top)[RH][PX],
             }
             if constexpr (NC > 0) add_xterms<PX, RW, T>(r, y, din, ccoef, cvec);
             emit(r, y);
-        });
+        };
+    apply_inplace<PX, RJ, R0, R1, R2, QMAX, FULLX, RH, T, Coef, decltype(xemit), SEG, Hook>(
+        d, top, bot, coef, lane, nx, xemit, hook);
 }
 
 // One application of the banded-Kronecker operator in "difference first" form,

@@ -148,13 +148,16 @@ struct CoopPlan {
     int stage = 0;   // how far planning got (diagnostics)
     size_t lds = 0, xh_bytes = 0, xn_bytes = 0, fl_bytes = 0, bytes = 0;
 };
-// variant: the workgroup shape (coop_variants), -1 the one the operator records
+// variant: the kernel variant (coop_variant_valid), -1 the one the operator
+// records
 hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan,
                      CoopKind kind = CoopKind::Expmv, int variant = -1);
-// Workgroup shapes of the cooperative Taylor kernel for this operator and
-// precision that apply the same arithmetic with the same rows per workgroup
-// (0: no kernel; variant 0 is the default).
-int coop_variants(const mg_ops* ops, int precision);
+// Variants of the cooperative Taylor kernel for an operator and precision;
+// all apply the same arithmetic per point in the same order with the same
+// rows per workgroup.  Bit 0 selects the alternative workgroup shape, bit 1
+// the exchange overlapped with the term's rows; variant 0 is the default.
+constexpr int MG_COOP_VARIANTS = 4;
+bool coop_variant_valid(const mg_ops* ops, int precision, int variant);
 // waves and rows per workgroup of a variant (false: none)
 bool coop_variant_shape(const mg_ops* ops, int precision, int variant, int* nw, int* rows);
 hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,
