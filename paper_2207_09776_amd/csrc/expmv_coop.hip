@@ -40,6 +40,17 @@ using namespace mgk;
 
 constexpr int kSpinLimit = 1 << 22;
 
+// The per-(path, step) tables are written by the assembly launch and only
+// read here: reading them through the constant address space lets the
+// compiler use scalar loads (through the scalar cache) for these wave-uniform
+// addresses, although the kernel stores to other global memory.
+template <class T>
+using ConstMem = __attribute__((address_space(4))) const T;
+template <class T>
+__device__ inline ConstMem<T>* as_const_mem(const T* p) {
+    return (ConstMem<T>*)p;
+}
+
 // Exchange area of a cooperative launch (in the caller's workspace, zeroed
 // before the launch) and the group layout.
 struct XArea {
@@ -528,10 +539,11 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
             const int m = tv.m();
             const double es = tv.es();
             pflag |= tv.flag();
-            const T* rows = tv.rows<T>() + (size_t)row0 * NBP;
+            const ConstMem<T>* rows = as_const_mem(tv.rows<T>() + (size_t)row0 * NBP);
             auto coef = [&](int r, int e) -> T { return rows[r * NBP + e]; };
             // x-term section of the table (after the nv_pad main rows)
-            const T* crows = tv.rows<T>() + (size_t)a.nv_pad * NBP + (size_t)row0 * ncb;
+            const ConstMem<T>* crows =
+                as_const_mem(tv.rows<T>() + (size_t)a.nv_pad * NBP + (size_t)row0 * ncb);
             auto ccoef = [&](int r, int e) -> T { return crows[r * ncb + e]; };
             int terms = 0;
             for (int sub = 0; sub < s && !cg.aborted; ++sub) {
@@ -976,10 +988,12 @@ __global__ __launch_bounds__(64 * NW) void euler_coop_kernel(EulerCoopArgs a) {
     }
     const XTerms<PX, T> cvec{a.nxt, a.xdesc, cvl, lane};
     __syncthreads();
-    const double* Brows = a.basis + (size_t)row0 * NBP;                  // basis matrix 0: B
-    const double* Arows = a.basis + ((size_t)a.nv_pad + row0) * NBP;     // basis matrix 1: A
-    const double* Bc = a.basis + (size_t)MG_NBASIS * a.nv_pad * NBP + (size_t)row0 * ncb;
-    const double* Ac = Bc + (size_t)a.nv_pad * ncb;
+    // basis matrices 0 (B) and 1 (A), read through the constant address space
+    const ConstMem<double>* Brows = as_const_mem(a.basis + (size_t)row0 * NBP);
+    const ConstMem<double>* Arows = as_const_mem(a.basis + ((size_t)a.nv_pad + row0) * NBP);
+    const ConstMem<double>* Bc =
+        as_const_mem(a.basis + (size_t)MG_NBASIS * a.nv_pad * NBP + (size_t)row0 * ncb);
+    const ConstMem<double>* Ac = Bc + (size_t)a.nv_pad * ncb;
 
     for (int64_t p = grp; p < a.P && !cg.aborted; p += a.x.ngroups) {
         double* src = a.u + (size_t)p * N;
@@ -1229,11 +1243,12 @@ hipError_t coop_info_classic(const mg_ops* ops, int precision, CoopKind kind, in
     const int qmax = ops->qmax;
     // alternative shapes (bit 0) exist for the Taylor kernel without
     // x-dependent factors, FP64 at 4 points per lane and FP32C at 8; the
-    // overlapped exchange (bit 1) for every Taylor kernel of the default shape
+    // overlapped exchange (bit 1) for every Taylor kernel whose waves hold
+    // more than 2 RH rows
     if (variant < 0 || variant >= MG_COOP_VARIANTS) return hipErrorInvalidValue;
     const bool ovl = (variant & 2) != 0;
     if ((variant & 1) &&
-        !(kind == CoopKind::Expmv && ops->ND == 0 && ops->NC == 0 && !ovl &&
+        !(kind == CoopKind::Expmv && ops->ND == 0 && ops->NC == 0 &&
           ((precision == MG_FP64 && sh.PX == 4) || (precision == MG_FP32C && sh.PX == 8))))
         return hipErrorInvalidValue;
     if (ovl && kind != CoopKind::Expmv) return hipErrorInvalidValue;
@@ -1371,9 +1386,19 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
         return e;
     plan->cus = cus;
     plan->stage = 5;
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * nw, lds)) != hipSuccess)
+    // a shape whose LDS exceeds a compute unit's is not planned (checked
+    // before the attribute call, which would leave a pending HIP error)
+    int lds_cu = 0;
+    if ((e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                   dev)) != hipSuccess)
         return e;
+    if (lds > (size_t)lds_cu) return hipErrorInvalidValue;
+    if ((e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) !=
+            hipSuccess ||
+        (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * nw, lds)) != hipSuccess) {
+        (void)hipGetLastError();   // the caller may go on with another shape
+        return e;
+    }
     plan->per_cu = per_cu;
     plan->stage = 6;
     const int resident = per_cu * cus;
