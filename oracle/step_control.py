@@ -22,6 +22,16 @@ returned, marked as not accepted.
 
 Per-path reading (select_steps_per_path): the same rule applied to each
 trajectory on its own, so that every path gets its own step size.
+
+Per-step reading (adaptive_path): the rule applied to each step of a path as
+the path is integrated.  The horizon is cut into K0 coarse steps of length
+h = T/K0.  From the state u at the start of coarse step k the step is taken
+as factor^l uniform sub-steps (l = 0, 1, ..., max_level) of orders 2 and 3
+with the same weights; the first l whose distance
+||u3 - u2||_F / ||u3||_F is <= tol is accepted (at l = max_level the step
+is accepted whatever its distance), the state moves on with u3, and a
+rejected level is redone from the same state with the step shortened by the
+factor.  A non-finite distance counts as +inf.
 """
 from __future__ import annotations
 
@@ -91,3 +101,51 @@ def padded_coefficients(dW: np.ndarray, T: float, K: Sequence[int], Kmax: int,
     for p in range(dW.shape[0]):
         out[p, :K[p]] = integrals.path_coefficients(dW[p:p + 1], T, int(K[p]), order)[0]
     return out
+
+
+def adaptive_path(basis: Sequence[sp.spmatrix], dW: np.ndarray, T: float, u0: np.ndarray,
+                  nx: int, nv: int, K0: int, factor: int, max_level: int,
+                  tol: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """One path (fine increments dW [Nf]): (uT, level [K0], gap [K0]) of the
+    per-step rule above."""
+    dW = np.asarray(dW, dtype=np.float64).reshape(-1)
+    Nf = dW.shape[0]
+    if K0 < 1 or Nf % K0 != 0 or factor < 2 or max_level < 0:
+        raise ValueError("K0 must divide the fine increments, factor >= 2, max_level >= 0")
+    n = Nf // K0
+    if n % factor ** max_level != 0:
+        raise ValueError("the finest sub-steps must divide a coarse step's increments")
+    h = T / K0
+    u = np.array(u0, dtype=np.float64, copy=True)
+    levels = np.zeros(K0, dtype=np.int64)
+    gaps = np.zeros(K0)
+    for k in range(K0):
+        seg = dW[k * n:(k + 1) * n][None, :]
+        for lev in range(max_level + 1):
+            m = factor ** lev
+            u2 = magnus.iterated_magnus(basis, integrals.path_coefficients(seg, h, m, 2)[0], u)
+            u3 = magnus.iterated_magnus(basis, integrals.path_coefficients(seg, h, m, 3)[0], u)
+            g = errors.relative_error(u3.reshape(nv, nx), u2.reshape(nv, nx))
+            if not np.isfinite(g):
+                g = np.inf
+            if g <= tol or lev == max_level:
+                levels[k], gaps[k] = lev, g
+                u = u3
+                break
+    return u, levels, gaps
+
+
+def adaptive_paths(basis: Sequence[sp.spmatrix], dW: np.ndarray, T: float, u0: np.ndarray,
+                   nx: int, nv: int, K0: int, factor: int, max_level: int,
+                   tol: float) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """adaptive_path for every path: dW [P][Nf], u0 [N] (shared) or [P][N]."""
+    dW = np.atleast_2d(dW)
+    u0 = np.asarray(u0, dtype=np.float64)
+    P = dW.shape[0]
+    uT = np.empty((P, nx * nv))
+    lv = np.zeros((P, K0), dtype=np.int64)
+    gp = np.zeros((P, K0))
+    for p in range(P):
+        uT[p], lv[p], gp[p] = adaptive_path(basis, dW[p], T, u0 if u0.ndim == 1 else u0[p],
+                                            nx, nv, K0, factor, max_level, tol)
+    return uT, lv, gp
