@@ -381,6 +381,41 @@ mg_status mg_select_magnus_steps_per_path(const mg_ops* ops2, const mg_ops* ops3
                                           void* stream);
 
 /* --------------------------------------------------------------------------
+ * mg_magnus_adaptive  (Remark "stepSizeControl", step by step along each path)
+ *
+ * Integrates every path with the step size controlled step by step: the
+ * horizon is cut into K0 coarse steps of h = T/K0; from the path's state at
+ * the start of coarse step k the step is taken as factor^l uniform
+ * sub-steps, l = 0, 1, ..., max_level, of orders 2 and 3 with the same
+ * (order-3) weights, and the first l whose distance
+ * ||u3 - u2||_F / ||u3||_F is <= tol is accepted (at l = max_level the step
+ * is accepted whatever its distance); the path continues from u3, and a
+ * rejected level is redone from the same state with the step shortened by
+ * the factor.  A flagged or non-finite step counts as an infinite distance.
+ * Every level runs as one batch over the paths still undecided.
+ *   ops2, ops3 : operators of orders 2 and 3 on the same grid and
+ *                coefficients.
+ *   dW         : device FP64 [P][Nf] fine increments over [0, T].
+ *   u0         : device FP64 [N] (u0_broadcast = 1) or [P][N].
+ *   uT         : device FP64 [P][N] output.
+ *   K0         : coarse steps, dividing Nf; factor >= 2; max_level in 0..20
+ *                with factor^max_level dividing Nf/K0.
+ *   levels     : host int32 [P][K0] output, the accepted level of each step.
+ *   gaps       : host FP64 [P][K0] output, its distance.
+ *   precision  : MG_FP64 or MG_FP32C (both orders run in it).
+ * A set-up call: it allocates its own device buffers and waits for the
+ * stream after every level.
+ * Errors: MG_EINVAL (NULL, orders not 2 and 3, different grids, K0 not
+ * dividing Nf, factor < 2, max_level out of range or factor^max_level not
+ * dividing Nf/K0, tol <= 0, T <= 0), MG_ESHAPE, MG_EUNSUPPORTED, MG_EHIP.
+ * ------------------------------------------------------------------------ */
+mg_status mg_magnus_adaptive(const mg_ops* ops2, const mg_ops* ops3, const double* dW, int64_t P,
+                             int64_t Nf, double T, const double* u0, int32_t u0_broadcast,
+                             double* uT, int32_t K0, int32_t factor, int32_t max_level,
+                             double tol, int32_t precision, int32_t* levels, double* gaps,
+                             void* stream);
+
+/* --------------------------------------------------------------------------
  * mg_euler_step  (eq. (EulerMaruyama))
  *
  * Runs NE Euler-Maruyama steps in place on every path:

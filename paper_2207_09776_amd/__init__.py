@@ -31,6 +31,7 @@ EXPORTS = ("mg_build_operators", "mg_free_operators", "mg_iterated_integrals",
            "mg_magnus_expmv_multi", "mg_autotune_expmv", "mg_autotune_cache_save",
            "mg_autotune_cache_load", "mg_select_magnus_steps",
            "mg_select_magnus_steps_per_path", "mg_iterated_integrals_steps",
+           "mg_magnus_adaptive",
            "mg_euler_increments",
            "mg_euler_workspace_bytes",
            "mg_euler_step",
@@ -99,6 +100,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                                     dbl, i32, vp, vp,
                                                     ctypes.POINTER(ctypes.c_int64), vp]
     lib.mg_iterated_integrals_steps.argtypes = [vp, i64, i64, dbl, vp, i32, i32, vp, vp, vp]
+    lib.mg_magnus_adaptive.argtypes = [vp, vp, vp, i64, i64, dbl, vp, i32, vp, i32, i32, i32,
+                                       dbl, i32, vp, vp, vp]
     lib.mg_autotune_expmv.argtypes = [vp, vp, i64, i32, vp, i32, vp, i32, dbl, vp, sz, i32,
                                       ctypes.c_char_p, sz, vp]
     lib.mg_autotune_cache_save.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
@@ -404,6 +407,32 @@ def select_magnus_steps_per_path(ops2: Operators, ops3: Operators, dW, T: float,
         int(Kmax), float(tol), PRECISIONS[precision], K.ctypes.data, gap.ctypes.data,
         ctypes.byref(nacc), _stream(stream)))
     return K, gap, int(nacc.value)
+
+
+@_stream_scoped
+def magnus_adaptive(ops2: Operators, ops3: Operators, dW, T: float, u0, K0: int,
+                    factor: int = 2, max_level: int = 3, tol: float = 1e-3,
+                    precision: str = "fp64", uT=None, stream=None):
+    """mg_magnus_adaptive: (uT [P][N], level [P][K0] int32, gap [P][K0]
+    float64), every coarse step of every path refined until its orders 2 and
+    3 agree within tol; dW [P][Nf], u0 [N] (shared) or [P][N]."""
+    import torch
+    _dev_f64(dW, "dW")
+    _dev_f64(u0, "u0")
+    P, Nf = dW.shape
+    N = ops2.grid.nx * ops2.grid.nv
+    bcast = 1 if u0.dim() == 1 else 0
+    if u0.numel() != (N if bcast else P * N):
+        raise ValueError("u0 has the wrong size")
+    if uT is None:
+        uT = torch.empty((P, N), dtype=torch.float64, device=dW.device)
+    level = np.zeros((P, K0), dtype=np.int32)
+    gap = np.zeros((P, K0), dtype=np.float64)
+    _check(load_library().mg_magnus_adaptive(
+        ops2.handle, ops3.handle, _ptr(dW), P, Nf, float(T), _ptr(u0), bcast, _ptr(uT),
+        int(K0), int(factor), int(max_level), float(tol), PRECISIONS[precision],
+        level.ctypes.data, gap.ctypes.data, _stream(stream)))
+    return uT, level, gap
 
 
 def _addr(t) -> Optional[int]:

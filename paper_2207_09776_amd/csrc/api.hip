@@ -910,6 +910,151 @@ mg_status mg_select_magnus_steps_per_path(const mg_ops* ops2, const mg_ops* ops3
     return MG_OK;
 }
 
+namespace {
+// dst row (dst_idx ? dst_idx[i] : i) = columns [off, off + len) of src row
+// (src_idx ? src_idx[i] : i), for i < n (a src_stride of 0 repeats one row)
+__global__ void copy_rows(const double* __restrict__ src, size_t src_stride, size_t off,
+                          const int32_t* __restrict__ src_idx, double* __restrict__ dst,
+                          size_t dst_stride, const int32_t* __restrict__ dst_idx, int64_t n,
+                          size_t len) {
+    const size_t total = (size_t)n * len;
+    for (size_t t = (size_t)blockIdx.x * 256 + threadIdx.x; t < total;
+         t += (size_t)gridDim.x * 256) {
+        const size_t i = t / len, c = t % len;
+        const size_t sr = src_idx ? (size_t)src_idx[i] : i;
+        const size_t dr = dst_idx ? (size_t)dst_idx[i] : i;
+        dst[dr * dst_stride + c] = src[sr * src_stride + off + c];
+    }
+}
+
+hipError_t launch_copy_rows(const double* src, size_t src_stride, size_t off,
+                            const int32_t* src_idx, double* dst, size_t dst_stride,
+                            const int32_t* dst_idx, int64_t n, size_t len, hipStream_t s) {
+    const size_t total = (size_t)n * len;
+    if (total == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_rows, dim3(blocks), dim3(256), 0, s, src, src_stride, off, src_idx,
+                       dst, dst_stride, dst_idx, n, len);
+    return hipGetLastError();
+}
+}  // namespace
+
+mg_status mg_magnus_adaptive(const mg_ops* ops2, const mg_ops* ops3, const double* dW, int64_t P,
+                             int64_t Nf, double T, const double* u0, int32_t u0_broadcast,
+                             double* uT, int32_t K0, int32_t factor, int32_t max_level,
+                             double tol, int32_t precision, int32_t* levels, double* gaps,
+                             void* stream) {
+    g_last_error.clear();
+    const std::string where = "mg_magnus_adaptive";
+    if (!levels || !gaps || !uT) return mg_fail(MG_EINVAL, where + ": NULL pointer");
+    StepLadder L{ops2, ops3, dW, u0, P, Nf, T, precision, stream};
+    // the ladder's checks (orders, grids, sizes, K0 | Nf, factor, tol, T)
+    mg_status st = L.check(where, K0, factor, K0, tol);
+    if (st != MG_OK) return st;
+    if (max_level < 0 || max_level > 20) return mg_fail(MG_EINVAL, where + ": max_level in 0..20");
+    int64_t mmax = 1;
+    for (int i = 0; i < max_level; ++i) mmax *= factor;
+    const int64_t n = Nf / K0;
+    if (mmax > (1 << 20) || n % mmax != 0)
+        return mg_fail(MG_EINVAL,
+                       where + ": factor^max_level must divide the fine increments of a step");
+    // buffers: the ladder's (coefficients for mmax sub-steps, u2, u3, distances,
+    // flags, expmv workspace) plus a slice of dW, the states of the active
+    // paths and three index lists
+    if ((st = L.allocate(where, (int32_t)mmax, 2, (int32_t)mmax)) != MG_OK) return st;
+    const size_t N = L.N;
+    double *dws = nullptr, *ucur = nullptr;
+    int32_t* idx = nullptr;
+    struct Free {
+        double** a;
+        double** b;
+        int32_t** c;
+        ~Free() {
+            if (*a) (void)hipFree(*a);
+            if (*b) (void)hipFree(*b);
+            if (*c) (void)hipFree(*c);
+        }
+    } release{&dws, &ucur, &idx};
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc((void**)&dws, (size_t)P * n * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&ucur, (size_t)P * N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc((void**)&idx, (size_t)P * 3 * sizeof(int32_t))) != hipSuccess)
+        return hip_fail(e, where.c_str());
+    // the state of every path starts as u0
+    if ((e = launch_copy_rows(u0, u0_broadcast ? 0 : N, 0, nullptr, uT, N, nullptr, P, N, s)) !=
+        hipSuccess)
+        return hip_fail(e, where.c_str());
+    const double h = T / K0;
+    std::vector<int32_t> active, acc_pos, acc_row, next;
+    for (int32_t k = 0; k < K0; ++k) {
+        active.resize((size_t)P);
+        for (int64_t p = 0; p < P; ++p) active[p] = (int32_t)p;
+        int64_t m = 1;
+        for (int32_t lev = 0; lev <= max_level && !active.empty(); ++lev, m *= factor) {
+            const int64_t A = (int64_t)active.size();
+            // the active paths' increments of this coarse step and their states
+            if ((e = hipMemcpyAsync(idx, active.data(), A * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = launch_copy_rows(dW, Nf, (size_t)k * n, idx, dws, n, nullptr, A, n, s)) !=
+                    hipSuccess ||
+                (e = launch_copy_rows(uT, N, 0, idx, ucur, N, nullptr, A, N, s)) != hipSuccess)
+                return hip_fail(e, where.c_str());
+            // orders 2 and 3 over m sub-steps (the order-3 weights; their
+            // first four are the order-2 ones), and their distances
+            if ((st = mg_iterated_integrals(dws, A, n, h, (int32_t)m, 3, L.coef, nullptr,
+                                            stream)) != MG_OK ||
+                (st = mg_magnus_expmv(ops2, L.coef, A, (int32_t)m, ucur, 0, L.u2, precision, 0.0,
+                                      L.ws, L.wsb, nullptr, L.fl, stream)) != MG_OK ||
+                (st = mg_magnus_expmv(ops3, L.coef, A, (int32_t)m, ucur, 0, L.u3, precision, 0.0,
+                                      L.ws, L.wsb, nullptr, L.fl + P, stream)) != MG_OK ||
+                (st = mg_error_vs_exact(&ops2->grid, nullptr, nullptr, L.u2, L.u3, A, 0, L.err,
+                                        stream)) != MG_OK)
+                return st;
+            if ((e = hipMemcpyAsync(L.herr.data(), L.err, A * sizeof(double),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(L.hfl.data(), L.fl, A * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(L.hfl.data() + P, L.fl + P, A * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return hip_fail(e, where.c_str());
+            // accept within tol (or at the last level): the order-3 state
+            // replaces the path's; the others are redone at the next level
+            acc_pos.clear();
+            acc_row.clear();
+            next.clear();
+            for (int64_t i = 0; i < A; ++i) {
+                const int32_t p = active[i];
+                double g = L.herr[i];
+                if (L.hfl[i] || L.hfl[P + i] || !std::isfinite(g))
+                    g = std::numeric_limits<double>::infinity();
+                if (g <= tol || lev == max_level) {
+                    levels[(size_t)p * K0 + k] = lev;
+                    gaps[(size_t)p * K0 + k] = g;
+                    acc_pos.push_back((int32_t)i);
+                    acc_row.push_back(p);
+                } else {
+                    next.push_back(p);
+                }
+            }
+            const int64_t nacc = (int64_t)acc_pos.size();
+            if (nacc > 0) {
+                if ((e = hipMemcpyAsync(idx + P, acc_pos.data(), nacc * sizeof(int32_t),
+                                        hipMemcpyHostToDevice, s)) != hipSuccess ||
+                    (e = hipMemcpyAsync(idx + 2 * P, acc_row.data(), nacc * sizeof(int32_t),
+                                        hipMemcpyHostToDevice, s)) != hipSuccess ||
+                    (e = launch_copy_rows(L.u3, N, 0, idx + P, uT, N, idx + 2 * P, nacc, N,
+                                          s)) != hipSuccess ||
+                    (e = hipStreamSynchronize(s)) != hipSuccess)
+                    return hip_fail(e, where.c_str());
+            }
+            active.swap(next);
+        }
+    }
+    return MG_OK;
+}
+
 size_t mg_workspace_bytes_multi(const mg_job* jobs, int32_t njobs) {
     if (!jobs || njobs <= 0) return 0;
     size_t total = 0;

@@ -140,3 +140,16 @@ def test_multi_job_argument_checks(lib):
     assert b"job 0" in lib.mg_last_error()
     assert lib.mg_workspace_bytes_multi(None, 1) == 0
     assert lib.mg_workspace_bytes_multi(jobs, 2) == 0
+
+
+def test_adaptive_argument_checks(lib):
+    """mg_magnus_adaptive rejects NULL outputs and operators before any
+    device call."""
+    vp = ctypes.c_void_p
+    lvl = (ctypes.c_int32 * 4)()
+    gp = (ctypes.c_double * 4)()
+    assert lib.mg_magnus_adaptive(None, None, vp(8), 1, 64, 1.0, vp(8), 1, vp(8), 4, 2, 1, 1e-3,
+                                  0, None, None, None) == mg.MG_EINVAL
+    assert lib.mg_magnus_adaptive(None, None, vp(8), 1, 64, 1.0, vp(8), 1, vp(8), 4, 2, 1, 1e-3,
+                                  0, lvl, gp, None) == mg.MG_EINVAL
+    assert b"NULL" in lib.mg_last_error()
