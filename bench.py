@@ -912,6 +912,27 @@ def main():
         fixed = np.array(m64["errs"][:R])
         fixed[neg] = np.array(rerun["attempts"][-1]["err"])
         rerun["mean_err_with_reruns"] = float(fixed.mean())
+        if w.order == 3 and uref is None:
+            # the same paths with the step size controlled step by step
+            # (orders 2 and 3 compared on every one of the K steps, a step
+            # redone with 2 or 4 sub-steps where they differ by more than
+            # 1e-3): only the steps that need it are refined
+            o2 = mg.build_operators(w.n, w.n, w.lo, w.hi, w.lo, w.hi, coeffs, 2)
+            ua, lv, gp = mg.magnus_adaptive(o2, ops, dWs, w.T, u0, K, 2, 2, 1e-3)
+            _, psa = mg.iterated_integrals(dWs, w.T, K, w.order)
+            ea = mg.error_vs_exact(ops, ua, pathstat=psa, a=w.a, sigma=w.sigma, s0sq=w.s0sq,
+                                   T=w.T)
+            torch.cuda.synchronize()
+            rerun["step_by_step"] = {
+                "K0": K, "factor": 2, "max_level": 2, "tol": 1e-3,
+                "err": [float(x) for x in ea.cpu().numpy()],
+                "refined_steps": [[int(k), int(lv[i, k])] for i in range(len(neg))
+                                  for k in range(K) if lv[i, k] > 0],
+                "sub_steps": [int((2 ** lv[i].astype(np.int64)).sum()) for i in range(len(neg))]}
+            o2.close()
+            log(f"negative-flagged paths step by step: err {rerun['step_by_step']['err']} with "
+                f"{rerun['step_by_step']['sub_steps']} sub-steps (refined [step, level]: "
+                f"{rerun['step_by_step']['refined_steps']})")
         log(f"negative-flagged paths {rerun['paths']}: err {rerun['err_before']} at K={K} -> "
             f"{rerun['attempts'][-1]['err']} at K={rerun['attempts'][-1]['K']}")
 
