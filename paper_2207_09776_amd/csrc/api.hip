@@ -273,12 +273,14 @@ mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32
         delete ops;
         return hip_fail(e, "mg_build_operators");
     }
-    // cooperative default: the overlapped exchange where it is built and the
-    // operator has no x-dependent parts (it was faster on every such shape
-    // measured; with x-factors or x-terms its register use varies by shape,
-    // so the autotuner decides there); the cache may override
+    // cooperative default: the overlapped exchange where it is built, the
+    // operator has no x-terms, and x-factors only above 256 points per row
+    // (it was faster on every such shape measured; with x-terms, and with
+    // x-factors at 4 points per lane, it spills, so the autotuner decides
+    // there); the cache may override
     for (int precision : {MG_FP64, MG_FP32C})
-        if (ops->ND == 0 && ops->NC == 0 && coop_variant_valid(ops, precision, 2))
+        if (ops->NC == 0 && (ops->ND == 0 || ops->grid.nx > 256) &&
+            coop_variant_valid(ops, precision, 2))
             ops->tuned_coop[precision == MG_FP32C ? 1 : 0] = 2;
     tune_cache_apply(ops);
     *out = ops;
