@@ -325,6 +325,34 @@ def run_mixed(args, w):
         log(f"group {g['n']}^2: Err {pg['mean_err']:.4e}, {pg['terms_per_path']:.0f} terms/path, "
             f"Taylor kernel {pg['launch_ms']:.3f} ms")
         del ws_g
+    # the same groups in FP64, each in a call of its own (the per-size FP64
+    # launches the mixed FP32C call stands against): time, error against the
+    # closed form and distance to the FP32C solution
+    fp64 = []
+    if prec == "fp32c":
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for g, pg in zip(groups, per_group):
+            ws_g = torch.empty(mg.workspace_bytes(g["ops"], g["P"], g["K"], "fp64"),
+                               dtype=torch.uint8, device=dev)
+            u32 = g["uT"].clone()
+            mg.magnus_expmv(g["ops"], g["coef"], g["u0"], precision="fp64", uT=g["uT"], ws=ws_g)
+            torch.cuda.synchronize()
+            e0.record()
+            mg.magnus_expmv(g["ops"], g["coef"], g["u0"], precision="fp64", uT=g["uT"], ws=ws_g)
+            e1.record()
+            torch.cuda.synchronize()
+            ms64 = e0.elapsed_time(e1)
+            err64 = mg.error_vs_exact(g["ops"], g["uT"], pathstat=g["ps"], a=w.a, sigma=w.sigma,
+                                      s0sq=w.s0sq, T=w.T)
+            dist = ((u32 - g["uT"]).norm(dim=1) / g["uT"].norm(dim=1)).max()
+            e64 = float(err64.mean())
+            fp64.append({"grid": g["n"], "paths": g["P"], "ms": ms64, "mean_err": e64,
+                         "fp32c_err_rel_diff": abs(pg["mean_err"] - e64) / e64,
+                         "fp32c_dist_max": float(dist), "fp32c_launch_ms": pg["launch_ms"]})
+            log(f"group {g['n']}^2 in FP64 alone: {ms64:.1f} ms (assembly + Taylor), Err "
+                f"{e64:.4e} (FP32C within {fp64[-1]['fp32c_err_rel_diff']:.2e} of it, distance "
+                f"{float(dist):.2e})")
+            del ws_g, u32
     dom = max(per_group, key=lambda pg: pg["launch_ms"])
     peak = FP32_VECTOR_PEAK if prec == "fp32c" else FP64_VECTOR_PEAK
     roofline = {"bound": "alu", "achieved": dom["achieved_TFLOPs"], "peak": peak / 1e12,
@@ -377,6 +405,7 @@ def run_mixed(args, w):
                    "initial": f"N(0,{w.s0sq} I)", "precision": prec,
                    "parallelism": "one mg_magnus_expmv_multi call per step, one GPU"},
         "groups": per_group,
+        "fp64_per_size": fp64 or None,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -17,6 +17,14 @@
 //   * after a second barrier the edge waves load their neighbours' halo rows
 //     and every wave loads the norms of all waves of all members, so every
 //     member takes the same early-termination decision.
+// The overlapped form (template flag OVL) synchronises per wave instead: each
+// wave has its own counter, bumps it once its stores of the term have
+// completed, polls all counters of its group and loads the halo rows and
+// norms while it computes the rows that read none of them (rows in the
+// segmented order of apply_inplace), and takes the stop decision after the
+// term; one workgroup barrier per term guards the LDS halo.  The arithmetic
+// per point and the decisions are those of the two-barrier form.
+//
 // Waiting is bounded: after kSpinLimit polls the launch is aborted through a
 // shared word, every workgroup leaves its loops and the paths get
 // MG_FLAG_ABORT.
@@ -210,7 +218,7 @@ struct CoopGroup {
             grp = b / x.G;
         }
         // this group's slices of the exchange area (offsets within them fit
-        // 32 bits: G <= 64 members)
+        // 32 bits: G <= 128 members)
         xh_g = reinterpret_cast<T*>(x.xh) + (size_t)grp * x.G * 2 * 2 * kRHX * (64 * PX);
         xn_g = x.xn + (size_t)grp * x.G * 2 * NW * 2;
     }
@@ -1096,8 +1104,9 @@ template <int PX, int RJ, int NW, int R0, int R1, int R2, int QMAX, bool FULLX, 
 hipError_t coop_kernel_info(const void** fn, size_t* lds, int* nw, int* rows) {
     using T = typename std::conditional<F32C, float, double>::type;
     constexpr int RH = halo_rows<R0, R1, R2, ND>();
-    if constexpr (OVL && RJ <= 2 * RH) {
-        // the overlapped exchange needs rows that read no halo row
+    if constexpr ((OVL && RJ <= 2 * RH) || RJ < RH) {
+        // the overlapped exchange needs rows that read no halo row; a wave
+        // publishes RH of its rows as halo
         return hipErrorInvalidValue;
     } else {
         *nw = NW;
@@ -1178,10 +1187,15 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
 // FP64 kernel without x-factors also runs 4 waves of 16 rows: it spills none
 // of its registers there, against 60 bytes per lane with 8 waves of 8 rows,
 // and its 4096-path 256^2 order-3 launch takes 1955 ms against 2000).  At nx > 512
-// (FP32C only) 4 waves of 6 rows: 24 rows per workgroup, so 43 members hold a
+// FP32C runs 4 waves of 6 rows: 24 rows per workgroup, so 43 members hold a
 // 1024-row path where 16-row workgroups need 64, and the exchange, which grows
-// with the member count, costs less.  The rows per workgroup (NW * RJ) depend
-// on nx only.  x-dependent factors up to nx = 512.
+// with the member count, costs less.  FP64 at nx > 512 runs 4 waves of 2 rows
+// (8 rows per workgroup, up to 128 members for 1024 rows): sixteen FP64
+// points per lane for the state, the term, the pending rows and the halo fit
+// 512 registers only with two rows per wave (three rows spill).  The table
+// rows are padded to the most rows per workgroup of any shape of the x width
+// (coop_rows_max), which every shape's row count divides.  x-dependent factors
+// up to nx = 512.
 #define MG_COOP_DISPATCH(CALL)                                                                 \
     {                                                                                          \
         const bool full = (ops->grid.nx == 64 * sh.PX);                                        \
@@ -1216,6 +1230,7 @@ hipError_t split_info(const mg_ops* ops, int precision, KInfo* ki) {
             }                                                                                  \
         }                                                                                      \
         if (sh.PX == 16 && f32 && !nd) { MG_COOP_FULLX(MG_COOP_SHAPES, 16, 6, 4, true, CALL) }  \
+        if (sh.PX == 16 && !f32 && !nd) { MG_COOP_FULLX(MG_COOP_SHAPES, 16, 2, 4, false, CALL) } \
         return hipErrorInvalidValue;                                                           \
     }
 
@@ -1376,7 +1391,7 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
     if (G * rows > ops->nv_pad) return hipErrorInvalidValue;   // tables shorter than the slabs
     plan->G = G;
     plan->stage = 2;
-    if (G < 1 || G > 64) return hipErrorInvalidValue;
+    if (G < 1 || G > 128) return hipErrorInvalidValue;
     plan->stage = 3;
     plan->lds = lds;
     int dev = 0, cus = 0, per_cu = 0;

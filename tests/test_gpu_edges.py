@@ -106,6 +106,8 @@ CONST_CASES = [
     # 24-row workgroups (nx > 512), ragged in x and in the last slab
     ("coop-520x40-m2-f32c", 520, 40, 2, 2, 2, 64, 0.002, "fp32c"),
     ("coop-1024x60-m3-f32c", 1024, 60, 3, 1, 2, 64, 0.0008, "fp32c"),
+    ("coop-1024x60-m3-f64", 1024, 60, 3, 1, 2, 64, 0.0008, "fp64"),
+    ("coop-600x45-m2-f64", 600, 45, 2, 1, 2, 64, 0.0008, "fp64"),
     ("coop-1000x50-m2-f32c", 1000, 50, 2, 1, 2, 64, 0.0008, "fp32c"),
 ]
 

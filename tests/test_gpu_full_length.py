@@ -80,12 +80,7 @@ def test_full_length_path_matches_oracle(name):
     ops, coef, u0 = batch(d)
     precs = ["fp64", "fp32c"]
     for prec in precs:
-        try:
-            uT, flags, _ = mg.magnus_expmv(ops, coef, u0, precision=prec)
-        except mg.MagnusError as ex:
-            # grids with no FP64 kernel (nx > 512) run the FP32 form only
-            assert prec == "fp64" and ex.code == mg.MG_EUNSUPPORTED and d["n"] > 512, str(ex)
-            continue
+        uT, flags, _ = mg.magnus_expmv(ops, coef, u0, precision=prec)
         torch.cuda.synchronize()
         p = d["path"]
         assert int(flags[p]) == 0

@@ -313,6 +313,10 @@ COOP_CASES = [
     # points empty, and 40 and 60 rows leave the last slab part empty
     ("coop-520x40-m2-f32c", 520, 40, -5.0, 5.0, 2, 2, 2, 256, 0.05, "fp32c", 1e-5),
     ("coop-1024x60-m3-f32c", 1024, 60, -5.0, 5.0, 3, 2, 2, 256, 0.02, "fp32c", 1e-5),
+    # FP64 above 512 points: workgroups of 2 rows x 4 waves, up to 128 per path
+    ("coop-520x40-m2-f64", 520, 40, -5.0, 5.0, 2, 2, 2, 256, 0.05, "fp64", 1e-10),
+    ("coop-1024x60-m3-f64", 1024, 60, -5.0, 5.0, 3, 2, 2, 256, 0.02, "fp64", 1e-10),
+    ("coop-700x1021-m2-f64", 700, 1021, -5.0, 5.0, 2, 1, 1, 64, 0.002, "fp64", 1e-10),
     # 8 paths: the plan places 8 groups, each on one XCD, and the members
     # exchange through that XCD's L2 (the other cases use agent scope)
     ("coop-256x256-m2-f64-p8", 256, 256, -5.0, 5.0, 2, 8, 2, 256, 0.05, "fp64", 1e-10),
