@@ -53,7 +53,7 @@ TRAFFIC = {
     ("68df813b853601cf", "const-128-p1024-m2-k16"): (133691 * 1024 * 2.000, 131110 * 1024 * 1.000),
     # profiles/expmv_coop_counters_const-256-p4096-m3-k32.txt (FP64 kernel with the
     # overlapped exchange, the variant the autotuner picks for this workload)
-    ("cd7a6ff41841eecb", "const-256-p4096-m3-k32"): (215892000 * 1024 * 2.000,
+    ("e7ff624451cf7b4c", "const-256-p4096-m3-k32"): (215936000 * 1024 * 2.000,
                                                      442074000 * 1024 * 1.000),
 }
 
