@@ -273,15 +273,16 @@ mg_status mg_build_operators(const mg_grid* grid, const mg_coeffs* coeffs, int32
         delete ops;
         return hip_fail(e, "mg_build_operators");
     }
-    // cooperative default: the overlapped exchange where it is built, the
-    // operator has no x-terms, and x-factors only above 256 points per row
-    // (it was faster on every such shape measured; with x-terms, and with
-    // x-factors at 4 points per lane, it spills, so the autotuner decides
-    // there); the cache may override
+    // cooperative default: the overlapped exchange where it is built for an
+    // operator without x-terms and spills no more than the two-barrier kernel
+    // (it was faster on every such shape measured; where it spills, and with
+    // x-terms, the autotuner decides); the cache may override
     for (int precision : {MG_FP64, MG_FP32C})
-        if (ops->NC == 0 && (ops->ND == 0 || ops->grid.nx > 256) &&
-            coop_variant_valid(ops, precision, 2))
-            ops->tuned_coop[precision == MG_FP32C ? 1 : 0] = 2;
+        if (ops->NC == 0 && coop_variant_valid(ops, precision, 2)) {
+            const int s2 = coop_variant_scratch(ops, precision, 2);
+            const int s0 = coop_variant_scratch(ops, precision, 0);
+            if (s2 >= 0 && s0 >= 0 && s2 <= s0) ops->tuned_coop[precision == MG_FP32C ? 1 : 0] = 2;
+        }
     tune_cache_apply(ops);
     *out = ops;
     return MG_OK;

@@ -516,11 +516,13 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
         apply_dir(std::false_type{}, d, top, bot, coef, ccoef, emit, NoHook{});
     };
     // overlapped exchange: in the segmented order no halo row is read before
-    // step RJ - 2RH; the wave bumps its counter before step IB, and before
-    // step IP polls the group, then loads the halo rows (LDS and the
-    // neighbours') and the norms, which arrive while steps IP .. RJ - 2RH - 1
-    // are computed
-    constexpr int IP = (RJ - 2 * RH - 3) > 1 ? (RJ - 2 * RH - 3) : 1;
+    // step RJ - 2RH; the wave bumps its counter before step IB and polls the
+    // group before step IP = RJ - 2RH, then loads the halo rows (LDS and the
+    // neighbours') and the norms.  Polling as late as that keeps the loaded
+    // rows out of the registers while the other rows are computed (an earlier
+    // poll made the 8-row waves spill: 1527 against 1426 ms on the 256^2
+    // workload), and the group's bumps have had half a term to arrive.
+    constexpr int IP = RJ - 2 * RH;
     constexpr int IB = IP / 2;
     static_assert(!OVL || (RJ > 2 * RH && IP <= RJ - 2 * RH), "overlapped exchange needs RJ > 2 RH");
     int hb = 0;   // LDS halo buffer of the overlapped form (alternates per term)
@@ -1368,6 +1370,17 @@ bool coop_variant_shape(const mg_ops* ops, int precision, int variant, int* nw, 
     *nw = ki.nw;
     *rows = ki.rows;
     return true;
+}
+
+int coop_variant_scratch(const mg_ops* ops, int precision, int variant) {
+    KInfo ki;
+    if (coop_info(ops, precision, CoopKind::Expmv, &ki, variant) != hipSuccess) return -1;
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, ki.fn) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return (int)at.localSizeBytes;
 }
 
 bool coop_variant_valid(const mg_ops* ops, int precision, int variant) {

@@ -158,6 +158,8 @@ hipError_t coop_plan(const mg_ops* ops, int precision, int64_t P, CoopPlan* plan
 // the exchange overlapped with the term's rows; variant 0 is the default.
 constexpr int MG_COOP_VARIANTS = 4;
 bool coop_variant_valid(const mg_ops* ops, int precision, int variant);
+// private (spill) bytes per lane of a variant's kernel (-1: no such kernel)
+int coop_variant_scratch(const mg_ops* ops, int precision, int variant);
 // waves and rows per workgroup of a variant (false: none)
 bool coop_variant_shape(const mg_ops* ops, int precision, int variant, int* nw, int* rows);
 hipError_t launch_expmv_coop(const mg_ops* ops, const char* tables, size_t tbytes, int64_t P,

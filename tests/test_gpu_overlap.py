@@ -1,6 +1,7 @@
 """The cooperative Taylor kernel with the overlapped group exchange (bit 1 of
 the cooperative kernel variants the autotuner times; the library's default
-for operators without x-terms, with x-factors above 256 points per row): each wave bumps its own
+for operators without x-terms where it spills no more than the two-barrier
+kernel): each wave bumps its own
 counter and polls its group while it computes the rows that read no halo
 row, then loads the halo rows and the norms; the rows are computed in the
 segmented order (rows RH .. RJ-1 first).  The arithmetic per point and the
@@ -131,6 +132,5 @@ def test_overlapped_exchange_matches_default_and_oracle(case, tmp_path):
     finally:
         # later operators of this key take the overlapped exchange only
         # where it is the default (no x-dependent parts)
-        set_cached_variant(cache, nx, nv, prec, order,
-                           OVL if cset == "const" or (cset == "xfactors" and nx > 256) else 0)
+        set_cached_variant(cache, nx, nv, prec, order, OVL if cset == "const" else 0)
         mg.autotune_cache_load(str(cache))
