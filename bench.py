@@ -52,9 +52,9 @@ TRAFFIC = {
     # profiles/expmv_resident_counters_const-128-p1024-m2-k16.txt
     ("68df813b853601cf", "const-128-p1024-m2-k16"): (133691 * 1024 * 2.000, 131110 * 1024 * 1.000),
     # profiles/expmv_coop_counters_const-256-p4096-m3-k32.txt (FP64 kernel with the
-    # overlapped exchange, the variant the autotuner picks for this workload)
-    ("e7ff624451cf7b4c", "const-256-p4096-m3-k32"): (215936000 * 1024 * 2.000,
-                                                     442074000 * 1024 * 1.000),
+    # overlapped exchange, 8 waves of 8 rows: the variant the autotuner picks here)
+    ("5ef2eefbd44ba240", "const-256-p4096-m3-k32"): (219381000 * 1024 * 2.000,
+                                                     467961000 * 1024 * 1.000),
 }
 
 
