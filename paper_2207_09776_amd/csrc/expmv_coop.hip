@@ -521,9 +521,12 @@ __global__ __launch_bounds__(64 * NW) void expmv_coop_kernel(CoopArgs a) {
     // neighbours') and the norms.  Polling as late as that keeps the loaded
     // rows out of the registers while the other rows are computed (an earlier
     // poll made the 8-row waves spill: 1527 against 1426 ms on the 256^2
-    // workload), and the group's bumps have had half a term to arrive.
+    // workload); bumping early, after one row (a quarter of the rows before
+    // the poll for the 16-row waves), gives the group's bumps the most time
+    // to arrive while leaving the publishing stores a row to complete (8-row
+    // waves: 1351 / 1309 / 1432 / 1584 ms with the bump before row 0 / 1 / 2 / 3).
     constexpr int IP = RJ - 2 * RH;
-    constexpr int IB = IP / 2;
+    constexpr int IB = IP >= 8 ? IP / 4 : (IP > 1 ? 1 : 0);
     static_assert(!OVL || (RJ > 2 * RH && IP <= RJ - 2 * RH), "overlapped exchange needs RJ > 2 RH");
     int hb = 0;   // LDS halo buffer of the overlapped form (alternates per term)
 
