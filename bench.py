@@ -762,9 +762,9 @@ def main():
     if args.paper_sweep:
         return paper_sweep(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: each path is independent "
-                                   "and a multi-GPU run would shard paths (see DESIGN.md); "
-                                   "--gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only: each path is independent, "
+                                   "so a run on several GPUs would give each a share of the paths "
+                                   "and add nothing per GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch

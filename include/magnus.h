@@ -45,7 +45,7 @@ typedef int32_t mg_status;
 #define MG_OK            0
 #define MG_EINVAL       (-1)   /* bad argument value or NULL pointer         */
 #define MG_ESHAPE       (-2)   /* inconsistent sizes                         */
-#define MG_EUNSUPPORTED (-3)   /* valid input this build does not implement  */
+#define MG_EUNSUPPORTED (-3)   /* valid input this library does not implement */
 #define MG_EHIP         (-4)   /* HIP runtime error                          */
 #define MG_ENOMEM       (-5)   /* host allocation failed / workspace too small */
 #define MG_ENONFINITE   (-6)   /* mg_check_flags: at least one path is flagged  */

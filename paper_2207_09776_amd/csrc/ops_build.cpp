@@ -566,7 +566,7 @@ mg_status mg_build_host(const mg_grid* g, const mg_coeffs* cf, int order, mg_ops
     if (!xterms.empty()) shape = std::max(shape, 1);   // built for the order-2 band shape
     if ((nd > 0 || !xterms.empty()) && shape > 1)
         return mg_fail(MG_EUNSUPPORTED,
-                       "x-dependent coefficients are built for band shapes up to (2,1,0) in this build");
+                       "x-dependent coefficients are built for band shapes up to (2,1,0) in this library");
     for (int q = 0; q < 3; ++q) R[q] = kShapes[shape][q];
     ops->qmax = kShapes[shape][3];
 
