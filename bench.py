@@ -55,6 +55,10 @@ TRAFFIC = {
     # overlapped exchange, 8 waves of 8 rows: the variant the autotuner picks here)
     ("c85861bdc18a52f4", "const-256-p4096-m3-k32"): (216825000 * 1024 * 2.000,
                                                      467961000 * 1024 * 1.000),
+    # profiles/expmv_coop_counters_mixed-64-256-1024-m2-fp32c.txt (the 1024^2 group's
+    # FP32C kernel with the overlapped exchange, 4 waves of 6 rows, 43 workgroups per path)
+    ("c85861bdc18a52f4", "mixed-64-256-1024-m2-fp32c"): (791436000 * 1024 * 2.000,
+                                                         1502296000 * 1024 * 1.000),
 }
 
 
@@ -215,6 +219,19 @@ def _mixed_oracle_worker(args):
     return time.perf_counter() - t0, errs
 
 
+def copy_calibration(torch, dev):
+    """One plain device copy of 1 GiB, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of a profiled run to bytes (the same run holds both)."""
+    src = torch.empty(2 ** 27, dtype=torch.float64, device=dev)     # 1 GiB
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: 1073741824 bytes read and written by one copy kernel")
+    del src, dst
+
+
 def run_mixed(args, w):
     """The mixed-size workload: groups of paths on grids of different sizes
     (constant-coefficient Langevin, FP32C), all in one mg_magnus_expmv_multi
@@ -224,6 +241,8 @@ def run_mixed(args, w):
     import workloads as wl
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        copy_calibration(torch, dev)
     coeffs = w.coefficients()
     groups = []
     for (n, paths, K, seed) in w.extra:
@@ -356,7 +375,9 @@ def run_mixed(args, w):
     dom = max(per_group, key=lambda pg: pg["launch_ms"])
     peak = FP32_VECTOR_PEAK if prec == "fp32c" else FP64_VECTOR_PEAK
     roofline = {"bound": "alu", "achieved": dom["achieved_TFLOPs"], "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": dom["achieved_TFLOPs"] * 1e12 / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": dom["achieved_TFLOPs"] * 1e12 / peak,
+                "traffic": traffic_for(w.name, "expmv_coop.hip" if dom["grid"] > 128
+                                       else "expmv_resident.hip"),
                 "kernel": ("expmv_coop_kernel" if dom["grid"] > 128 else "expmv_resident_kernel")
                           + f" ({dom['grid']}^2 group)",
                 "flops_per_point_term": 2 * NNZ_ROW[w.order] + 2, "launch_ms": dom["launch_ms"]}
@@ -823,14 +844,7 @@ def main():
         return flags, st
 
     if args.copy_calibration:
-        src = torch.empty(2 ** 27, dtype=torch.float64, device=dev)     # 1 GiB
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: 1073741824 bytes read and written by one copy kernel")
-        del src, dst
+        copy_calibration(torch, dev)
 
     def measure(precision, steps, warmup):
         """Warm-up (with Taylor statistics), then `steps` timed passes."""
