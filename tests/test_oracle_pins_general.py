@@ -194,6 +194,36 @@ def test_v_derivative_noise_with_x_dependence_splits_into_columns(order):
     assert _rel(got, want) <= 1e-12
 
 
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_x_dependent_x_terms_with_v_noise_factor_exactly(order):
+    """B = I (x) L_x with L_x = diag(h(x)) + diag(f^x(x)) D^x + 1/2 diag(g^xx(x)) D^xx
+    and A = A_v (x) I with A_v = diag(sigma^v(v)) D^v: x-dependent coefficients
+    of x derivatives and noise through d/dv in one problem.  B and A act on
+    different factors, so they commute, every commutator of the Magnus basis
+    vanishes and the step exponentials multiply to one: orders 2 and 3 give
+    exp(T B + W_T A - (T/2) A^2) = exp(W_T A_v - (T/2) A_v^2) (x) exp(T L_x),
+    order 1 (exponent B h + A W_h per step, no A^2 term) exp(W_T A_v) (x)
+    exp(T L_x); on the [nv][nx] grid (x fastest) U_T = E_v U_0 E_x^T.
+    Pins the H, f^x and g^xx branches with x dependence
+    together with the sigma^v branch: their Kronecker slots, the x-fast
+    stacking of x-dependent grids, and that no cross terms enter the basis."""
+    h = lambda x, v: 0.2 * np.sin(x) + 0 * v
+    fx = lambda x, v: 0.5 + 0.3 * np.cos(x) + 0 * v
+    gxx = lambda x, v: 0.8 + 0.2 * np.sin(1.7 * x) + 0 * v
+    sv = lambda x, v: 0.4 + 0.1 * v + 0 * x
+    coeffs = {"h": _grid_array(h), "fx": _grid_array(fx), "gxx": _grid_array(gxx),
+              "sv": _grid_array(sv)}
+    got, WT = _oracle_path(coeffs, order)
+    x, v, dx, dv = _nodes()
+    Lx = (np.diag(h(x, 0.0)) + np.diag(fx(x, 0.0)) @ _d1(NX, dx)
+          + 0.5 * np.diag(gxx(x, 0.0)) @ _d2(NX, dx))
+    Av = np.diag(sv(0.0, v)) @ _d1(NV, dv)
+    Ev = scipy.linalg.expm(WT * Av - (0.5 * T * Av @ Av if order >= 2 else 0.0))
+    Ex = scipy.linalg.expm(T * Lx)
+    want = Ev @ _u0() @ Ex.T
+    assert _rel(got, want) <= 1e-12
+
+
 def test_constant_potential_is_a_scalar_factor():
     """H = h constant commutes with every matrix: the Langevin path with H
     added equals e^{hT} times the path without it (catches a sign or a factor
