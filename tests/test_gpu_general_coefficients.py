@@ -12,7 +12,9 @@ every edge row and column (uniform random u0): 1e-10 relative (Frobenius) and
 max-norm per path, orders 1 to 3 where the basis exists, register-resident
 (40 x 36) and cooperative (200 x 150) kernels; Euler-Maruyama (B and A with
 x-terms) within 1e-12.  Reported unsupported: sigma^x at order 3 (three x
-derivatives meet in [[B,A],A]) and FP32C.
+derivatives meet in [[B,A],A]), x-dependent H, f^x and g^xx with
+v-dependent noise at order 3 (v bands of the factors beyond the kernels'
+shapes) and FP32C.
 """
 import sys
 
@@ -49,6 +51,12 @@ SETS = {
                 sv=lambda x, v: 0.5 + 0 * x), (1, 2, 3)),
     "gxv-x": (C(fx=lambda x, v: -v, gxv=lambda x, v: 0.1 * phi(x) + 0 * v,
                 gvv=lambda x, v: 1.0 + 0 * x, sv=lambda x, v: 0.5 + 0 * x), (1, 2, 3)),
+    # x-dependent H, f^x and g^xx beside v-dependent diffusion and noise
+    "x-part-v-noise": (C(h=lambda x, v: 0.2 * np.sin(x) + 0 * v,
+                         fx=lambda x, v: 0.5 + 0.3 * np.cos(x) + 0 * v,
+                         gxx=lambda x, v: 0.3 * (1 + phi(x)) + 0 * v,
+                         gvv=lambda x, v: 1.0 + 0 * x,
+                         sv=lambda x, v: 0.4 + 0.1 * np.tanh(v) + 0 * x), (1, 2)),
 }
 GRIDS = [(40, 36, 0.01), (200, 150, 0.0015)]
 CASES = [(name, order, nx, nv, T) for name, (_, orders) in SETS.items() for order in orders
@@ -122,6 +130,11 @@ def test_general_coefficients_unsupported_forms_are_reported():
     say("general coefficients: unsupported forms")
     with pytest.raises(mg.MagnusError) as ex:
         build("sx-x", 40, 36, 3)
+    assert ex.value.code == mg.MG_EUNSUPPORTED
+    # v-dependent noise meeting x-dependent factors in [[B,A],A]: v bands
+    # beyond the kernels' factor shapes
+    with pytest.raises(mg.MagnusError) as ex:
+        build("x-part-v-noise", 40, 36, 3)
     assert ex.value.code == mg.MG_EUNSUPPORTED
     ops = build("gxx-x", 40, 36, 2)
     coef = torch.zeros((1, 1, 6), dtype=torch.float64, device=DEV)
